@@ -1,0 +1,190 @@
+/*
+ * stp.h -- C ABI of the MI355X (gfx950) S-TPLS channel-flow time step.
+ *
+ * The library advances the incompressible Navier-Stokes equations for
+ * pressure-driven flow in a channel (periodic in x and y, no-slip walls at
+ * z = 0 and z = lz, constant mean pressure gradient dp/dx) with the method of
+ * Fannon et al., arXiv 1511.07800:
+ *   - MAC staggered finite volumes with centred differences (Sec. 3.1, 3.2);
+ *   - optional Smagorinsky eddy viscosity with Van Driest wall damping
+ *     (Sec. 2.2, definitions of nu_t, Delta and phi_w);
+ *   - projection: predictor u* with third-order Adams-Bashforth for the
+ *     convection and the "convective-like" viscous part and Crank-Nicolson
+ *     for the "diffusive" viscous part, then the pressure Poisson equation
+ *     and the correction u = u* - dt grad p (Sec. 3.1);
+ *   - the Poisson equation solved by Scheduled Relaxation Jacobi: cycles of
+ *     M Jacobi-SOR sweeps with scheduled weights omega_k, repeated until the
+ *     residual test passes (Sec. 3.4, Jacobi-SOR equation).
+ * Beside the paper's FP64 method the library offers a mixed mode (FP32
+ * relaxation sweeps inside an FP64 defect correction).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid: nx*ny*nz cells of size dx = lx/nx, dy = ly/ny, dz = lz/nz.  Fields
+ * are flat arrays, x fastest: index(i,j,k) = i + nx*(j + ny*k).
+ *   u  x-faces at (i dx, (j+1/2) dy, (k+1/2) dz), nx*ny*nz values
+ *   v  y-faces at ((i+1/2) dx, j dy, (k+1/2) dz), nx*ny*nz values
+ *   w  z-faces at ((i+1/2) dx, (j+1/2) dy, k dz), k = 0..nz: nx*ny*(nz+1)
+ *      values; planes k = 0 and k = nz are the walls and are kept at 0
+ *   p, nu_T and the Poisson right-hand side at cell centres, nx*ny*nz.
+ * Units are physical: the caller gives nu and dp/dx, never a Reynolds number.
+ *
+ * Memory: the caller allocates ONE device workspace of stp_workspace_bytes()
+ * bytes (any allocator; 256-byte alignment) and keeps it alive until
+ * stp_destroy().  The library carves every field and work array out of it and
+ * never allocates device memory itself; it allocates a small pinned host
+ * buffer for scalar read-back.  Pointers returned by stp_fields() are borrowed
+ * views into the workspace.
+ *
+ * Streams: all device work is enqueued on cfg->stream (a hipStream_t; NULL is
+ * the null stream).  stp_step() and stp_poisson_solve() synchronise that
+ * stream only at residual checks and to fill their statistics; fields are
+ * valid in stream order.
+ *
+ * Errors: every call returns an stp_status; nothing throws, aborts or exits.
+ * stp_last_error() gives a message for the last failure on a context.  A
+ * device fault surfaces as STP_EDEVICE at the next synchronisation.
+ *
+ * Threads: a context may be used by one host thread at a time.  Contexts are
+ * independent.
+ */
+#ifndef STP_H
+#define STP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STP_ABI_VERSION 1
+
+typedef struct stp_ctx stp_ctx; /* opaque */
+
+typedef enum {
+    STP_OK = 0,
+    STP_EINVAL = -1,   /* bad argument or configuration */
+    STP_ENOMEM = -2,   /* workspace too small or pinned host allocation failed */
+    STP_EDEVICE = -3,  /* a HIP call failed (launch, copy or a device fault) */
+    STP_ENOCONV = -4,  /* Poisson solve hit its cycle limit; p holds the last iterate */
+    STP_ENAN = -5      /* non-finite residual */
+} stp_status;
+
+typedef enum {
+    STP_FP64 = 0,  /* every sweep and reduction in FP64 (the paper's method) */
+    STP_MIXED = 1  /* FP32 relaxation sweeps inside an FP64 defect correction */
+} stp_precision;
+
+typedef enum {
+    STP_WS_PREV = 0,  /* Poisson solve starts from p^n */
+    STP_WS_ZERO = 1   /* Poisson solve starts from 0 */
+} stp_warm;
+
+typedef enum {
+    STP_U = 0, STP_V = 1, STP_W = 2, STP_P = 3, STP_NUT = 4, STP_RHS = 5
+} stp_field;
+
+typedef enum { STP_DTYPE_F64 = 0, STP_DTYPE_F32 = 1 } stp_dtype;
+
+typedef struct {
+    int32_t nx, ny, nz;        /* cells; nx, ny >= 1, nz >= 2 */
+    int32_t les;               /* 0: nu_T = nu (DNS); 1: Smagorinsky + Van Driest */
+    double lx, ly, lz;         /* domain lengths (> 0) */
+    double nu;                 /* molecular kinematic viscosity (> 0) */
+    double dpdx;               /* G = dp/dx, constant; G < 0 drives flow in +x */
+    double dt;                 /* time step (> 0) */
+    double cs;                 /* Smagorinsky coefficient C_S (paper: 0.1) */
+    double vd_a;               /* Van Driest constant A (paper: 25) */
+    int32_t precision;         /* stp_precision */
+    int32_t warm_start;        /* stp_warm */
+    double poisson_rtol;       /* stop when ||b - L p||_2 <= rtol ||b||_2; 0: run exactly maxit cycles */
+    int32_t poisson_maxit;     /* cycle limit (FP64 cycles, or defect-correction passes in mixed mode) */
+    int32_t srj_m;             /* length of a caller-given cycle; 0 selects the built-in schedule */
+    const double* srj_omega;   /* host array of srj_m weights in sweep order (copied at init) */
+    double srj_reduction;      /* built-in schedule: bound on one cycle's error reduction (e.g. 1e-3) */
+    int32_t mixed_inner;       /* mixed mode: FP32 cycles per defect-correction pass (>= 1) */
+    int32_t tblock;            /* sweeps fused per relaxation launch: 1, 2 or 4 (0 selects 1) */
+    double cn_tol;             /* Crank-Nicolson iteration error target relative to the start (e.g. 1e-13) */
+    void* stream;              /* hipStream_t for all work */
+} stp_config;
+
+typedef struct {
+    int32_t cycles;    /* SRJ cycles run (FP64 cycles, or FP32 inner cycles in mixed mode) */
+    int32_t outer;     /* residual checks after the first (defect-correction passes in mixed mode) */
+    int32_t sweeps;    /* relaxation sweeps run */
+    int32_t status;    /* stp_status of the solve */
+    double relres0;    /* ||b - L p0||_2 / ||b||_2 before the solve */
+    double relres;     /* after the solve */
+    double bnorm;      /* ||b||_2 */
+} stp_solve_stats;
+
+typedef struct {
+    stp_solve_stats poisson;
+    int32_t step;      /* steps completed by this context */
+    int32_t cn_sweeps; /* Crank-Nicolson iterations per component */
+    double max_div;    /* max |div u^{n+1}| over all cells */
+    double u_bulk;     /* mean of u over all x-faces */
+    double u_max;      /* max |u| */
+    double cfl;        /* max(|u| dt/dx, |v| dt/dy, |w| dt/dz) */
+    double u_centre;   /* mean u on the channel centreline z = lz/2 */
+    double nut_max;    /* max nu_T */
+    double ms_total;   /* wall time of the step (stream-ordered events), ms */
+    double ms_poisson; /* of which the Poisson solve, ms */
+} stp_step_stats;
+
+/* Bytes of device workspace the configuration needs (0 if cfg is invalid). */
+size_t stp_workspace_bytes(const stp_config* cfg);
+
+/* Validate cfg, carve the workspace, build the SRJ schedule and zero every
+ * field (state at rest, p = 0, empty Adams-Bashforth history, step 0).
+ * STP_EINVAL on a bad configuration, STP_ENOMEM if bytes is too small.
+ * On success *out owns a context to release with stp_destroy(). */
+stp_status stp_init(const stp_config* cfg, void* dev_workspace, size_t bytes, stp_ctx** out);
+
+/* Advance nsteps time steps (Sec. 3.1): eddy viscosity (if les), explicit
+ * terms, Crank-Nicolson predictor, b = div(u*)/dt minus its mean, SRJ solve
+ * for p from the warm start, p minus its mean, correction, diagnostics.
+ * Stops at the first step whose solve fails and returns its status
+ * (STP_ENOCONV leaves the step completed with the last iterate).
+ * last (nullable) receives the statistics of the last step taken. */
+stp_status stp_step(stp_ctx* ctx, int32_t nsteps, stp_step_stats* last);
+
+/* Solve L_p p = b (Sec. 3.1 Poisson equation, zero normal gradient at the
+ * walls, periodic in x and y) with the context's schedule and precision.
+ * b_dev: device FP64 array of nx*ny*nz values, mean-free (borrowed, read).
+ * p_dev: device FP64 array, initial guess in, solution out (mean removed).
+ * rtol, maxit as in stp_config.  stats nullable.  Returns STP_OK,
+ * STP_ENOCONV, STP_ENAN or an error. */
+stp_status stp_poisson_solve(stp_ctx* ctx, const void* b_dev, void* p_dev, double rtol, int32_t maxit,
+                             stp_solve_stats* stats);
+
+/* Apply an explicit list of Jacobi-SOR sweeps (Sec. 3.4):
+ * p <- p + (omega_s / D)(L_p p - b) for s = 0..nsweeps-1, with
+ * D = 2/dx^2 + 2/dy^2 + 2/dz^2.  dtype selects FP64 or FP32 arrays for
+ * b_dev and p_dev (nx*ny*nz values each, borrowed).  omega is a host array.
+ * Uses the context's fused-sweep setting.  Enqueues only; no sync. */
+stp_status stp_relax(stp_ctx* ctx, int32_t dtype, const void* b_dev, void* p_dev, const double* omega,
+                     int32_t nsweeps);
+
+/* ||b - L_p p||_2 in FP64 for FP64 device arrays (synchronises). */
+stp_status stp_residual_norm(stp_ctx* ctx, const void* b_dev, const void* p_dev, double* norm);
+
+/* Borrowed view of a field: device pointer, shape {nz or nz+1, ny, nx}
+ * (slowest first) and dtype.  STP_W has nz+1 planes. */
+stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape[3], int32_t* dtype);
+
+/* The relaxation cycle in use: writes min(cap, M) weights, *m = M. */
+stp_status stp_schedule(const stp_ctx* ctx, double* omega, int32_t cap, int32_t* m);
+
+/* Release the context (not the caller's workspace). NULL is accepted. */
+stp_status stp_destroy(stp_ctx* ctx);
+
+/* Message for the last failure on ctx ("" if none); valid until the next call. */
+const char* stp_last_error(const stp_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STP_H */

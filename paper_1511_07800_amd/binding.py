@@ -1,0 +1,210 @@
+"""ctypes binding of libstp.so (include/stp.h): argument marshalling only."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libstp.so")
+
+STP_OK, STP_EINVAL, STP_ENOMEM, STP_EDEVICE, STP_ENOCONV, STP_ENAN = 0, -1, -2, -3, -4, -5
+STP_FP64, STP_MIXED = 0, 1
+STP_WS_PREV, STP_WS_ZERO = 0, 1
+STP_U, STP_V, STP_W, STP_P, STP_NUT, STP_RHS = range(6)
+STP_DTYPE_F64, STP_DTYPE_F32 = 0, 1
+
+_STATUS = {0: "STP_OK", -1: "STP_EINVAL", -2: "STP_ENOMEM", -3: "STP_EDEVICE", -4: "STP_ENOCONV", -5: "STP_ENAN"}
+
+
+class StpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("les", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+                ("nu", ctypes.c_double), ("dpdx", ctypes.c_double), ("dt", ctypes.c_double),
+                ("cs", ctypes.c_double), ("vd_a", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("poisson_rtol", ctypes.c_double), ("poisson_maxit", ctypes.c_int32),
+                ("srj_m", ctypes.c_int32), ("srj_omega", ctypes.POINTER(ctypes.c_double)),
+                ("srj_reduction", ctypes.c_double), ("mixed_inner", ctypes.c_int32), ("tblock", ctypes.c_int32),
+                ("cn_tol", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int32), ("outer", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("relres0", ctypes.c_double), ("relres", ctypes.c_double),
+                ("bnorm", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("poisson", SolveStats), ("step", ctypes.c_int32), ("cn_sweeps", ctypes.c_int32),
+                ("max_div", ctypes.c_double), ("u_bulk", ctypes.c_double), ("u_max", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("u_centre", ctypes.c_double), ("nut_max", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("ms_poisson", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "poisson"}
+        d["poisson"] = self.poisson.as_dict()
+        return d
+
+
+_lib = None
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libstp.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(python paper_1511_07800_amd/build.py)")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.stp_workspace_bytes.argtypes = [ctypes.POINTER(Config)]
+    L.stp_workspace_bytes.restype = ctypes.c_size_t
+    L.stp_init.argtypes = [ctypes.POINTER(Config), vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.stp_init.restype = i32
+    L.stp_step.argtypes = [vp, i32, ctypes.POINTER(StepStats)]
+    L.stp_step.restype = i32
+    L.stp_poisson_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(SolveStats)]
+    L.stp_poisson_solve.restype = i32
+    L.stp_relax.argtypes = [vp, i32, vp, vp, ctypes.POINTER(dbl), i32]
+    L.stp_relax.restype = i32
+    L.stp_residual_norm.argtypes = [vp, vp, vp, ctypes.POINTER(dbl)]
+    L.stp_residual_norm.restype = i32
+    L.stp_fields.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
+    L.stp_fields.restype = i32
+    L.stp_schedule.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
+    L.stp_schedule.restype = i32
+    L.stp_destroy.argtypes = [vp]
+    L.stp_destroy.restype = i32
+    L.stp_last_error.argtypes = [vp]
+    L.stp_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Channel:
+    """One library context: a channel-flow state living in a torch-allocated workspace.
+
+    Parameters follow ``stp_config`` (include/stp.h).  ``omega`` optionally gives
+    the relaxation cycle; None selects the library's built-in schedule.
+    """
+
+    def __init__(self, nx, ny, nz, lx, ly, lz, nu, dpdx, dt, les=0, cs=0.1, vd_a=25.0,
+                 precision=STP_FP64, warm_start=STP_WS_PREV, poisson_rtol=1e-10, poisson_maxit=1000,
+                 omega=None, srj_reduction=1e-3, mixed_inner=1, tblock=1, cn_tol=1e-13, device=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self._omega_keep = None
+        cfg = Config()
+        cfg.nx, cfg.ny, cfg.nz, cfg.les = nx, ny, nz, les
+        cfg.lx, cfg.ly, cfg.lz = lx, ly, lz
+        cfg.nu, cfg.dpdx, cfg.dt, cfg.cs, cfg.vd_a = nu, dpdx, dt, cs, vd_a
+        cfg.precision, cfg.warm_start = precision, warm_start
+        cfg.poisson_rtol, cfg.poisson_maxit = poisson_rtol, poisson_maxit
+        if omega is not None:
+            arr = (ctypes.c_double * len(omega))(*[float(x) for x in omega])
+            self._omega_keep = arr
+            cfg.srj_m = len(omega)
+            cfg.srj_omega = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+        else:
+            cfg.srj_m = 0
+            cfg.srj_omega = None
+        cfg.srj_reduction, cfg.mixed_inner, cfg.tblock, cfg.cn_tol = srj_reduction, mixed_inner, tblock, cn_tol
+        cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        self.cfg = cfg
+        nbytes = self.lib.stp_workspace_bytes(ctypes.byref(cfg))
+        if nbytes == 0:
+            raise StpError(STP_EINVAL, "invalid configuration")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_off = (-base) % 256
+        h = ctypes.c_void_p()
+        rc = self.lib.stp_init(ctypes.byref(cfg), ctypes.c_void_p(base + self._ws_off), nbytes, ctypes.byref(h))
+        if rc != STP_OK:
+            raise StpError(rc, "stp_init failed")
+        self.handle = h
+        self.shape = (nz, ny, nx)
+        self.nx, self.ny, self.nz = nx, ny, nz
+
+    # -- helpers ---------------------------------------------------------
+    def _check(self, rc, what, allow=()):
+        if rc != STP_OK and rc not in allow:
+            msg = self.lib.stp_last_error(self.handle).decode()
+            raise StpError(rc, f"{what}: {msg}")
+        return rc
+
+    def field(self, which):
+        """Borrowed torch view (float64) of a library field."""
+        ptr = ctypes.c_void_p()
+        shape = (ctypes.c_int64 * 3)()
+        dt = ctypes.c_int32()
+        self._check(self.lib.stp_fields(self.handle, which, ctypes.byref(ptr), shape, ctypes.byref(dt)), "stp_fields")
+        n = shape[0] * shape[1] * shape[2]
+        off = ptr.value - self.workspace.data_ptr()
+        return self.workspace[off:off + 8 * n].view(self.torch.float64).view(shape[0], shape[1], shape[2])
+
+    def schedule(self):
+        m = ctypes.c_int32()
+        self._check(self.lib.stp_schedule(self.handle, None, 0, ctypes.byref(m)), "stp_schedule")
+        arr = (ctypes.c_double * m.value)()
+        self._check(self.lib.stp_schedule(self.handle, arr, m.value, ctypes.byref(m)), "stp_schedule")
+        return list(arr)
+
+    # -- entry points ------------------------------------------------------
+    def step(self, nsteps=1, allow=()):
+        st = StepStats()
+        rc = self.lib.stp_step(self.handle, int(nsteps), ctypes.byref(st))
+        self._check(rc, "stp_step", allow)
+        return st.as_dict()
+
+    def poisson_solve(self, b, p, rtol, maxit, allow=()):
+        assert b.dtype == self.torch.float64 and p.dtype == self.torch.float64
+        assert b.is_contiguous() and p.is_contiguous() and b.numel() == p.numel() == self.nx * self.ny * self.nz
+        st = SolveStats()
+        rc = self.lib.stp_poisson_solve(self.handle, _dptr(b), _dptr(p), float(rtol), int(maxit), ctypes.byref(st))
+        self._check(rc, "stp_poisson_solve", allow)
+        return st.as_dict(), rc
+
+    def relax(self, b, p, omega):
+        t = self.torch
+        assert b.dtype == p.dtype and b.dtype in (t.float64, t.float32)
+        assert b.is_contiguous() and p.is_contiguous() and b.numel() == p.numel() == self.nx * self.ny * self.nz
+        dtype = STP_DTYPE_F64 if b.dtype == t.float64 else STP_DTYPE_F32
+        arr = (ctypes.c_double * max(1, len(omega)))(*[float(x) for x in omega])
+        self._check(self.lib.stp_relax(self.handle, dtype, _dptr(b), _dptr(p), arr, len(omega)), "stp_relax")
+
+    def residual_norm(self, b, p):
+        out = ctypes.c_double()
+        self._check(self.lib.stp_residual_norm(self.handle, _dptr(b), _dptr(p), ctypes.byref(out)),
+                    "stp_residual_norm")
+        return out.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.stp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,671 @@
+// C ABI of the S-TPLS time step (declared in include/stp.h): context,
+// workspace carving, the SRJ schedule, the Poisson drivers and the step
+// sequence.  All arithmetic runs in the kernels of stp_kernels.hip; this file
+// only orders launches on the caller's stream and reads back scalars.
+#include "stp.h"
+#include "stp_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace stp;
+
+struct stp_ctx {
+    stp_config cfg{};
+    Geo g{};
+    hipStream_t s = nullptr;
+    int device = 0;
+    // FP64 fields
+    double *u = nullptr, *v = nullptr, *w = nullptr, *p = nullptr, *ptmp = nullptr, *b = nullptr, *nut = nullptr;
+    double* rhs[3] = {nullptr, nullptr, nullptr};
+    double* tmp = nullptr;  // Crank-Nicolson ping-pong partner (nw values)
+    double* e[3][3] = {};   // Adams-Bashforth history, [slot][component]
+    // FP32 work arrays of the mixed solve
+    float *e0 = nullptr, *e1 = nullptr, *r32 = nullptr;
+    double* part = nullptr;  // reduction partials
+    double* res = nullptr;   // device scalar results
+    double* host = nullptr;  // pinned host copy of res
+    std::vector<double> omega;  // the relaxation cycle (weights)
+    double D = 0.0;             // Jacobi diagonal 2/dx^2 + 2/dy^2 + 2/dz^2
+    int step = 0;
+    hipEvent_t ev[4] = {};
+    std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// Effective configuration: defaults applied to the zero-valued optional fields.
+stp_config effective(const stp_config& c)
+{
+    stp_config e = c;
+    if (e.srj_reduction == 0.0) e.srj_reduction = 1e-3;
+    if (e.mixed_inner == 0) e.mixed_inner = 1;
+    if (e.tblock == 0) e.tblock = 1;
+    if (e.cn_tol == 0.0) e.cn_tol = 1e-13;
+    return e;
+}
+
+const char* validate(const stp_config& c)
+{
+    if (c.nx < 1 || c.ny < 1 || c.nz < 2) return "grid: need nx >= 1, ny >= 1, nz >= 2";
+    if ((long long)c.nx * c.ny * (c.nz + 1) > (1LL << 40)) return "grid too large";
+    if (!finite_pos(c.lx) || !finite_pos(c.ly) || !finite_pos(c.lz)) return "domain lengths must be finite and > 0";
+    if (!finite_pos(c.nu)) return "nu must be finite and > 0";
+    if (!finite_pos(c.dt)) return "dt must be finite and > 0";
+    if (!std::isfinite(c.dpdx)) return "dpdx must be finite";
+    if (c.les != 0 && c.les != 1) return "les must be 0 or 1";
+    if (c.les && (!(c.cs >= 0.0) || !std::isfinite(c.cs) || !finite_pos(c.vd_a))) return "les: need cs >= 0, vd_a > 0";
+    if (c.precision != STP_FP64 && c.precision != STP_MIXED) return "precision must be STP_FP64 or STP_MIXED";
+    if (c.warm_start != STP_WS_PREV && c.warm_start != STP_WS_ZERO) return "warm_start must be STP_WS_PREV or STP_WS_ZERO";
+    if (!(c.poisson_rtol >= 0.0) || !std::isfinite(c.poisson_rtol)) return "poisson_rtol must be >= 0";
+    if (c.poisson_maxit < 1) return "poisson_maxit must be >= 1";
+    if (c.srj_m < 0) return "srj_m must be >= 0";
+    if (c.srj_m > 0) {
+        if (!c.srj_omega) return "srj_omega is NULL with srj_m > 0";
+        for (int k = 0; k < c.srj_m; ++k)
+            if (!std::isfinite(c.srj_omega[k])) return "srj_omega holds a non-finite weight";
+    } else if (!(c.srj_reduction > 0.0 && c.srj_reduction < 1.0)) {
+        return "srj_reduction must lie in (0, 1)";
+    }
+    if (c.mixed_inner < 1) return "mixed_inner must be >= 1";
+    if (c.tblock != 1) return "tblock must be 1";
+    if (!(c.cn_tol > 0.0 && c.cn_tol < 1.0)) return "cn_tol must lie in (0, 1)";
+    return nullptr;
+}
+
+// Byte offsets of every array in the workspace.
+struct Layout {
+    size_t u, v, w, p, ptmp, b, nut, rhs[3], tmp, e[3][3], e0, e1, r32, part, res, total;
+};
+
+Layout layout(const stp_config& c)
+{
+    const size_t n = (size_t)c.nx * c.ny * c.nz, nw = (size_t)c.nx * c.ny * (c.nz + 1);
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.u = take(n * 8);
+    L.v = take(n * 8);
+    L.w = take(nw * 8);
+    L.p = take(n * 8);
+    L.ptmp = take(n * 8);
+    L.b = take(n * 8);
+    L.nut = take(n * 8);
+    for (int q = 0; q < 3; ++q) L.rhs[q] = take((q == 2 ? nw : n) * 8);
+    L.tmp = take(nw * 8);
+    for (int sl = 0; sl < 3; ++sl)
+        for (int q = 0; q < 3; ++q) L.e[sl][q] = take((q == 2 ? nw : n) * 8);
+    L.e0 = take(n * 4);
+    L.e1 = take(n * 4);
+    L.r32 = take(n * 4);
+    L.part = take((size_t)kMaxPartBlocks * 8 * 8);
+    L.res = take(RES_COUNT * 8);
+    L.total = off;
+    return L;
+}
+
+// ---- the relaxation schedule ------------------------------------------------
+// The paper (Sec. 3.4) uses an SRJ cycle of M Jacobi-SOR sweeps whose weights
+// it takes from an external script without printing them.  The built-in
+// cycle here: one sweep multiplies the error along an eigenvector of -L_p
+// (eigenvalue lambda, kappa = lambda/D) by (1 - omega kappa), so the cycle of
+// least worst-case factor over [kappa_min, kappa_max] has omega_k = 1/x_k at
+// the Chebyshev nodes x_k of that interval (the many-level limit of SRJ).
+// M is the smallest degree whose bound 1/T_M((b+a)/(b-a)) meets the requested
+// reduction; the sweeps run in Leja order of the nodes, which keeps the
+// intermediate amplification of the cycle moderate.
+
+void kappa_range(const Geo& g, double D, double* kmin, double* kmax)
+{
+    const double pi = M_PI;
+    double lmin = INFINITY, lmax = 0.0;
+    auto dir = [&](double ih2, int n, bool cosine_modes) {
+        if (n < 2) return;  // a single cell carries only the constant mode
+        const double period = cosine_modes ? 2.0 * n : (double)n;
+        const double s1 = std::sin(pi / period);
+        lmin = std::min(lmin, 4.0 * ih2 * s1 * s1);
+        const int mtop = cosine_modes ? n - 1 : n / 2;
+        const double st = std::sin(pi * mtop / period);
+        lmax += 4.0 * ih2 * st * st;
+    };
+    dir(g.idx2, g.nx, false);
+    dir(g.idy2, g.ny, false);
+    dir(g.idz2, g.nz, true);
+    *kmin = lmin / D;
+    *kmax = lmax / D;
+}
+
+std::vector<double> chebyshev_leja_cycle(double a, double b, double reduction)
+{
+    const double s = (b + a) / (b - a);
+    const int m = std::max(1, (int)std::ceil(std::acosh(1.0 / reduction) / std::acosh(s)));
+    std::vector<double> x(m);
+    for (int k = 1; k <= m; ++k) x[k - 1] = 0.5 * (a + b) + 0.5 * (b - a) * std::cos(M_PI * (2.0 * k - 1.0) / (2.0 * m));
+    // Leja order: largest magnitude first, then maximise the product of
+    // distances to the nodes already placed (sum of logs).  Candidates within
+    // a relative 1e-9 of the best count as tied (the nodes are symmetric, so
+    // exact ties occur and round-off must not decide them); ties go to the
+    // lower index.
+    std::vector<char> used(m, 0);
+    std::vector<double> logd(m, 0.0);
+    std::vector<double> out;
+    out.reserve(m);
+    int cur = 0;
+    for (int k = 1; k < m; ++k)
+        if (std::fabs(x[k]) > std::fabs(x[cur])) cur = k;
+    for (int t = 0; t < m; ++t) {
+        used[cur] = 1;
+        out.push_back(1.0 / x[cur]);
+        if (t == m - 1) break;
+        double top = -INFINITY;
+        for (int k = 0; k < m; ++k) {
+            if (used[k]) continue;
+            logd[k] += std::log(std::fabs(x[k] - x[cur]));
+            top = std::max(top, logd[k]);
+        }
+        const double tol = 1e-9 * std::max(1.0, std::fabs(top));
+        int best = -1;
+        for (int k = 0; k < m && best < 0; ++k)
+            if (!used[k] && logd[k] >= top - tol) best = k;
+        cur = best;
+    }
+    return out;
+}
+
+#define CHK(expr)                                                                   \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);           \
+            return STP_EDEVICE;                                                     \
+        }                                                                           \
+    } while (0)
+
+stp_status readback(stp_ctx* ctx)
+{
+    CHK(hipMemcpyAsync(ctx->host, ctx->res, RES_COUNT * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+    CHK(hipStreamSynchronize(ctx->s));
+    return STP_OK;
+}
+
+// Run `count` sweeps of the schedule starting at sweep index `first` (mod M),
+// ping-ponging between *cur and *other; on return *cur holds the iterate.
+template <typename T>
+stp_status run_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, const double* omega, int m, long long first,
+                      long long count)
+{
+    const int tb = ctx->cfg.tblock;
+    long long s = 0;
+    while (s < count) {
+        const int nf = (int)std::min<long long>(tb, count - s);
+        Weights wts{};
+        for (int f = 0; f < nf; ++f) wts.c[f] = omega[(first + s + f) % m] / ctx->D;
+        if (nf == 1 || tb == 1) {
+            for (int f = 0; f < nf; ++f) {
+                Weights one{};
+                one.c[0] = wts.c[f];
+                CHK(relax<T>(ctx->g, b, *cur, *other, one, 1, ctx->s));
+                std::swap(*cur, *other);
+            }
+        } else {
+            CHK(relax<T>(ctx->g, b, *cur, *other, wts, nf, ctx->s));
+            std::swap(*cur, *other);
+        }
+        s += nf;
+    }
+    return STP_OK;
+}
+
+// FP64 SRJ solve of L_p p = b; p and ptmp ping-pong; result lands in p.
+// Assumes res[RES_B2] = ||b||^2 already computed.
+stp_status solve_fp64(stp_ctx* ctx, const double* b, double* p, double* ptmp, double rtol, int maxit,
+                      stp_solve_stats* st)
+{
+    const int m = (int)ctx->omega.size();
+    double* cur = p;
+    double* oth = ptmp;
+    stp_status rc;
+    CHK(residual(ctx->g, b, cur, nullptr, ctx->part, ctx->res, ctx->s));
+    if ((rc = readback(ctx)) != STP_OK) return rc;
+    const double bn = std::sqrt(ctx->host[RES_B2]);
+    const double fb = bn > 1e-300 ? bn : 1e-300;
+    double rn = std::sqrt(ctx->host[RES_R2]);
+    st->bnorm = bn;
+    st->relres0 = rn / fb;
+    st->status = STP_OK;
+    int cycles = 0, checks = 0;
+    if (rtol > 0.0) {
+        while (!(rn <= rtol * fb)) {
+            if (!std::isfinite(rn)) { st->status = STP_ENAN; break; }
+            if (cycles >= maxit) { st->status = STP_ENOCONV; break; }
+            if ((rc = run_sweeps<double>(ctx, b, &cur, &oth, ctx->omega.data(), m, 0, m)) != STP_OK) return rc;
+            ++cycles;
+            CHK(residual(ctx->g, b, cur, nullptr, ctx->part, ctx->res, ctx->s));
+            if ((rc = readback(ctx)) != STP_OK) return rc;
+            rn = std::sqrt(ctx->host[RES_R2]);
+            ++checks;
+        }
+    } else {
+        if ((rc = run_sweeps<double>(ctx, b, &cur, &oth, ctx->omega.data(), m, 0, (long long)m * maxit)) != STP_OK)
+            return rc;
+        cycles = maxit;
+        CHK(residual(ctx->g, b, cur, nullptr, ctx->part, ctx->res, ctx->s));
+        if ((rc = readback(ctx)) != STP_OK) return rc;
+        rn = std::sqrt(ctx->host[RES_R2]);
+        checks = 1;
+        if (!std::isfinite(rn)) st->status = STP_ENAN;
+    }
+    if (cur != p) CHK(copy(p, cur, ctx->g.n, ctx->s));
+    CHK(sum_into(p, ctx->g.n, ctx->part, ctx->res, RES_SUM_P, ctx->s));
+    CHK(remove_mean(p, ctx->g.n, ctx->res + RES_SUM_P, -1, ctx->part, ctx->res, ctx->s));
+    st->relres = rn / fb;
+    st->cycles = cycles;
+    st->outer = checks;
+    st->sweeps = cycles * m;
+    return STP_OK;
+}
+
+// Mixed solve: FP64 residual r = b - L p, FP32 SRJ cycles on L e = r from
+// e = 0, FP64 update p += e, repeated until the FP64 residual test passes.
+stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, int maxit, stp_solve_stats* st)
+{
+    const int m = (int)ctx->omega.size();
+    const int inner = ctx->cfg.mixed_inner;
+    stp_status rc;
+    CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s));
+    if ((rc = readback(ctx)) != STP_OK) return rc;
+    const double bn = std::sqrt(ctx->host[RES_B2]);
+    const double fb = bn > 1e-300 ? bn : 1e-300;
+    double rn = std::sqrt(ctx->host[RES_R2]);
+    st->bnorm = bn;
+    st->relres0 = rn / fb;
+    st->status = STP_OK;
+    int outer = 0;
+    auto pass = [&]() -> stp_status {
+        float* cur = ctx->e0;
+        float* oth = ctx->e1;
+        CHK(fill(cur, 0.0f, ctx->g.n, ctx->s));
+        stp_status r2 = run_sweeps<float>(ctx, ctx->r32, &cur, &oth, ctx->omega.data(), m, 0, (long long)m * inner);
+        if (r2 != STP_OK) return r2;
+        CHK(add_correction(p, cur, ctx->g.n, ctx->s));
+        CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s));
+        r2 = readback(ctx);
+        if (r2 != STP_OK) return r2;
+        rn = std::sqrt(ctx->host[RES_R2]);
+        ++outer;
+        return STP_OK;
+    };
+    if (rtol > 0.0) {
+        while (!(rn <= rtol * fb)) {
+            if (!std::isfinite(rn)) { st->status = STP_ENAN; break; }
+            if (outer >= maxit) { st->status = STP_ENOCONV; break; }
+            if ((rc = pass()) != STP_OK) return rc;
+        }
+    } else {
+        for (int it = 0; it < maxit; ++it)
+            if ((rc = pass()) != STP_OK) return rc;
+        if (!std::isfinite(rn)) st->status = STP_ENAN;
+    }
+    CHK(sum_into(p, ctx->g.n, ctx->part, ctx->res, RES_SUM_P, ctx->s));
+    CHK(remove_mean(p, ctx->g.n, ctx->res + RES_SUM_P, -1, ctx->part, ctx->res, ctx->s));
+    st->relres = rn / fb;
+    st->cycles = outer * inner;
+    st->outer = outer;
+    st->sweeps = outer * inner * m;
+    return STP_OK;
+}
+
+stp_status solve(stp_ctx* ctx, const double* b, double* p, double rtol, int maxit, stp_solve_stats* st)
+{
+    if (ctx->cfg.precision == STP_MIXED) return solve_mixed(ctx, b, p, rtol, maxit, st);
+    return solve_fp64(ctx, b, p, ctx->ptmp, rtol, maxit, st);
+}
+
+stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
+{
+    const stp_config& c = ctx->cfg;
+    const Geo& g = ctx->g;
+    hipStream_t s = ctx->s;
+    stp_step_stats st{};
+    stp_status rc;
+    CHK(hipEventRecord(ctx->ev[0], s));
+    CHK(zero_walls(g, ctx->w, s));
+
+    // 1. eddy viscosity at level n (Sec. 2.2)
+    double nut_max = c.nu;
+    if (c.les) {
+        const double delta = 2.0 * std::cbrt((c.lx / c.nx) * (c.ly / c.ny) * (c.lz / c.nz));
+        const double utau = std::sqrt(0.5 * c.lz * std::fabs(c.dpdx));
+        const double inv_wall_unit = utau / (c.nu * c.vd_a);
+        CHK(nut_smagorinsky(g, ctx->u, ctx->v, ctx->w, ctx->nut, c.nu, c.cs * delta, inv_wall_unit, c.lz, ctx->part,
+                            ctx->res, s));
+    } else {
+        CHK(fill(ctx->nut, c.nu, g.n, s));
+    }
+
+    // 2. explicit terms and Crank-Nicolson right-hand sides (Sec. 3.1)
+    const int n = ctx->step;
+    const int sl_n = n % 3, sl_1 = (n + 2) % 3, sl_2 = (n + 1) % 3;
+    double beta[3] = {1.0, 0.0, 0.0};
+    if (n == 1) { beta[0] = 1.5; beta[1] = -0.5; }
+    if (n >= 2) { beta[0] = 23.0 / 12.0; beta[1] = -16.0 / 12.0; beta[2] = 5.0 / 12.0; }
+    double* vel[3] = {ctx->u, ctx->v, ctx->w};
+    for (int q = 0; q < 3; ++q) {
+        MomArgs a{};
+        a.u = ctx->u; a.v = ctx->v; a.w = ctx->w; a.nut = ctx->nut;
+        a.en = ctx->e[sl_n][q]; a.e1 = ctx->e[sl_1][q]; a.e2 = ctx->e[sl_2][q];
+        a.rhs = ctx->rhs[q];
+        a.beta0 = beta[0]; a.beta1 = beta[1]; a.beta2 = beta[2];
+        a.dt = c.dt; a.half_dt = 0.5 * c.dt; a.dpdx = c.dpdx; a.nu = c.nu;
+        CHK(momentum_rhs(g, q, a, s));
+    }
+    if (c.les) {
+        if ((rc = readback(ctx)) != STP_OK) return rc;
+        nut_max = ctx->host[RES_NUT_MAX];
+        if (!std::isfinite(nut_max)) {
+            ctx->err = "non-finite eddy viscosity";
+            return STP_ENAN;
+        }
+    }
+
+    // 3. Crank-Nicolson solve (I - dt/2 L_nu) u* = R by the iteration
+    //    x <- x + (R - (I - h L) x)/(1 + h s), h = dt/2, s = Lambda/2, Lambda =
+    //    4 nu_max (1/dx^2 + 1/dy^2 + 1/dz^2) >= spectral radius of -L_nu; its
+    //    error contracts by rho = h s/(1 + h s) per iteration, so m iterations
+    //    with rho^m <= cn_tol reach the target.  m is made odd so that the
+    //    last iterate lands in the state array.
+    const double lam = 4.0 * nut_max * (g.idx2 + g.idy2 + g.idz2);
+    const double hs = 0.5 * c.dt * 0.5 * lam;
+    const double rho = hs / (1.0 + hs);
+    int mcn = (int)std::ceil(std::log(c.cn_tol) / std::log(rho));
+    mcn = std::max(1, std::min(mcn, 999));
+    if (mcn % 2 == 0) ++mcn;
+    for (int q = 0; q < 3; ++q) {
+        for (int it = 0; it < mcn; ++it) {
+            const double* x = it == 0 ? ctx->rhs[q] : (it % 2 == 1 ? vel[q] : ctx->tmp);
+            double* xo = it % 2 == 0 ? vel[q] : ctx->tmp;
+            CHK(cn_iterate(g, q, ctx->nut, c.nu, ctx->rhs[q], x, xo, 0.5 * c.dt, 1.0 / (1.0 + hs), s));
+        }
+    }
+    st.cn_sweeps = mcn;
+
+    // 4. b = div(u*)/dt, mean removed; ||b||^2 into RES_B2
+    CHK(divergence_rhs(g, ctx->u, ctx->v, ctx->w, ctx->b, 1.0 / c.dt, ctx->part, ctx->res, s));
+    CHK(remove_mean(ctx->b, g.n, ctx->res + RES_SUM_B, RES_B2, ctx->part, ctx->res, s));
+
+    // 5. SRJ pressure solve from the warm start (Sec. 3.4)
+    if (c.warm_start == STP_WS_ZERO) CHK(fill(ctx->p, 0.0, g.n, s));
+    CHK(hipEventRecord(ctx->ev[1], s));
+    if ((rc = solve(ctx, ctx->b, ctx->p, c.poisson_rtol, c.poisson_maxit, &st.poisson)) != STP_OK) return rc;
+    CHK(hipEventRecord(ctx->ev[2], s));
+
+    // 6. correction u = u* - dt grad p (Sec. 3.1)
+    CHK(project(g, ctx->p, ctx->u, ctx->v, ctx->w, c.dt, s));
+
+    // 7. diagnostics
+    CHK(diagnostics(g, ctx->u, ctx->v, ctx->w, c.dt, ctx->part, ctx->res, s));
+    CHK(hipEventRecord(ctx->ev[3], s));
+    if ((rc = readback(ctx)) != STP_OK) return rc;
+    st.max_div = ctx->host[RES_DIAG + 0];
+    st.u_bulk = ctx->host[RES_DIAG + 1] / (double)g.n;
+    st.u_max = ctx->host[RES_DIAG + 2];
+    st.cfl = ctx->host[RES_DIAG + 3];
+    st.u_centre = ctx->host[RES_DIAG + 4] / (double)g.plane;
+    st.nut_max = nut_max;
+    float ms = 0.f;
+    CHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
+    st.ms_total = ms;
+    CHK(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+    st.ms_poisson = ms;
+    ++ctx->step;
+    st.step = ctx->step;
+    if (out) *out = st;
+    return (stp_status)st.poisson.status;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t stp_workspace_bytes(const stp_config* cfg)
+{
+    if (!cfg) return 0;
+    const stp_config c = effective(*cfg);
+    if (validate(c)) return 0;
+    return layout(c).total;
+}
+
+stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out)
+{
+    if (!cfg || !out) return STP_EINVAL;
+    *out = nullptr;
+    const stp_config c = effective(*cfg);
+    if (validate(c)) return STP_EINVAL;
+    const Layout L = layout(c);
+    if (!ws || bytes < L.total) return STP_ENOMEM;
+    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return STP_EINVAL;
+    stp_ctx* ctx = new (std::nothrow) stp_ctx();
+    if (!ctx) return STP_ENOMEM;
+    ctx->cfg = c;
+    ctx->cfg.srj_omega = nullptr;  // copied below; the caller's array is not kept
+    ctx->s = static_cast<hipStream_t>(c.stream);
+    Geo& g = ctx->g;
+    g.nx = c.nx; g.ny = c.ny; g.nz = c.nz;
+    g.plane = (long long)c.nx * c.ny;
+    g.n = g.plane * c.nz;
+    g.nw = g.plane * (c.nz + 1);
+    const double dx = c.lx / c.nx, dy = c.ly / c.ny, dz = c.lz / c.nz;
+    g.idx = 1.0 / dx; g.idy = 1.0 / dy; g.idz = 1.0 / dz;
+    g.idx2 = 1.0 / (dx * dx); g.idy2 = 1.0 / (dy * dy); g.idz2 = 1.0 / (dz * dz);
+    ctx->D = 2.0 * (g.idx2 + g.idy2 + g.idz2);
+    char* base = static_cast<char*>(ws);
+    ctx->u = (double*)(base + L.u);
+    ctx->v = (double*)(base + L.v);
+    ctx->w = (double*)(base + L.w);
+    ctx->p = (double*)(base + L.p);
+    ctx->ptmp = (double*)(base + L.ptmp);
+    ctx->b = (double*)(base + L.b);
+    ctx->nut = (double*)(base + L.nut);
+    for (int q = 0; q < 3; ++q) ctx->rhs[q] = (double*)(base + L.rhs[q]);
+    ctx->tmp = (double*)(base + L.tmp);
+    for (int sl = 0; sl < 3; ++sl)
+        for (int q = 0; q < 3; ++q) ctx->e[sl][q] = (double*)(base + L.e[sl][q]);
+    ctx->e0 = (float*)(base + L.e0);
+    ctx->e1 = (float*)(base + L.e1);
+    ctx->r32 = (float*)(base + L.r32);
+    ctx->part = (double*)(base + L.part);
+    ctx->res = (double*)(base + L.res);
+    if (c.srj_m > 0) {
+        ctx->omega.assign(c.srj_omega, c.srj_omega + c.srj_m);
+    } else {
+        double a, b;
+        kappa_range(g, ctx->D, &a, &b);
+        if (!(a > 0.0 && b > a)) {
+            delete ctx;
+            return STP_EINVAL;
+        }
+        ctx->omega = chebyshev_leja_cycle(a, b, c.srj_reduction);
+    }
+    if (hipGetDevice(&ctx->device) != hipSuccess || hipHostMalloc((void**)&ctx->host, RES_COUNT * sizeof(double)) != hipSuccess) {
+        delete ctx;
+        return STP_ENOMEM;
+    }
+    for (int q = 0; q < 4; ++q)
+        if (hipEventCreate(&ctx->ev[q]) != hipSuccess) {
+            stp_destroy(ctx);
+            return STP_EDEVICE;
+        }
+    // state at rest, empty history
+    hipError_t e = hipSuccess;
+    const long long nn = g.n, nw = g.nw;
+    double* zero64[] = {ctx->u, ctx->v, ctx->p, ctx->ptmp, ctx->b, ctx->rhs[0], ctx->rhs[1]};
+    for (double* a : zero64) if (e == hipSuccess) e = fill(a, 0.0, nn, ctx->s);
+    if (e == hipSuccess) e = fill(ctx->w, 0.0, nw, ctx->s);
+    if (e == hipSuccess) e = fill(ctx->rhs[2], 0.0, nw, ctx->s);
+    if (e == hipSuccess) e = fill(ctx->tmp, 0.0, nw, ctx->s);
+    if (e == hipSuccess) e = fill(ctx->nut, c.nu, nn, ctx->s);
+    for (int sl = 0; sl < 3; ++sl)
+        for (int q = 0; q < 3; ++q)
+            if (e == hipSuccess) e = fill(ctx->e[sl][q], 0.0, q == 2 ? nw : nn, ctx->s);
+    float* zero32[] = {ctx->e0, ctx->e1, ctx->r32};
+    for (float* a : zero32) if (e == hipSuccess) e = fill(a, 0.0f, nn, ctx->s);
+    if (e == hipSuccess) e = fill(ctx->res, 0.0, RES_COUNT, ctx->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->s);
+    if (e != hipSuccess) {
+        stp_destroy(ctx);
+        return STP_EDEVICE;
+    }
+    *out = ctx;
+    return STP_OK;
+}
+
+stp_status stp_step(stp_ctx* ctx, int32_t nsteps, stp_step_stats* last)
+{
+    if (!ctx) return STP_EINVAL;
+    if (nsteps < 0) {
+        ctx->err = "nsteps must be >= 0";
+        return STP_EINVAL;
+    }
+    ctx->err.clear();
+    for (int t = 0; t < nsteps; ++t) {
+        stp_status rc = one_step(ctx, last);
+        if (rc != STP_OK) {
+            if (ctx->err.empty()) ctx->err = rc == STP_ENOCONV ? "Poisson solve did not converge" : "Poisson residual is not finite";
+            return rc;
+        }
+    }
+    return STP_OK;
+}
+
+stp_status stp_poisson_solve(stp_ctx* ctx, const void* b_dev, void* p_dev, double rtol, int32_t maxit,
+                             stp_solve_stats* stats)
+{
+    if (!ctx) return STP_EINVAL;
+    ctx->err.clear();
+    if (!b_dev || !p_dev || !(rtol >= 0.0) || !std::isfinite(rtol) || maxit < 1) {
+        ctx->err = "stp_poisson_solve: bad argument";
+        return STP_EINVAL;
+    }
+    const double* b = static_cast<const double*>(b_dev);
+    double* p = static_cast<double*>(p_dev);
+    CHK(sumsq_into(b, ctx->g.n, ctx->part, ctx->res, RES_B2, ctx->s));
+    stp_solve_stats st{};
+    stp_status rc = solve(ctx, b, p, rtol, maxit, &st);
+    if (rc != STP_OK) return rc;
+    if (stats) *stats = st;
+    if (st.status != STP_OK)
+        ctx->err = st.status == STP_ENOCONV ? "Poisson solve did not converge" : "Poisson residual is not finite";
+    return (stp_status)st.status;
+}
+
+stp_status stp_relax(stp_ctx* ctx, int32_t dtype, const void* b_dev, void* p_dev, const double* omega, int32_t nsweeps)
+{
+    if (!ctx) return STP_EINVAL;
+    ctx->err.clear();
+    if (!b_dev || !p_dev || nsweeps < 0 || (nsweeps > 0 && !omega) || (dtype != STP_DTYPE_F64 && dtype != STP_DTYPE_F32)) {
+        ctx->err = "stp_relax: bad argument";
+        return STP_EINVAL;
+    }
+    for (int k = 0; k < nsweeps; ++k)
+        if (!std::isfinite(omega[k])) {
+            ctx->err = "stp_relax: non-finite weight";
+            return STP_EINVAL;
+        }
+    stp_status rc;
+    if (dtype == STP_DTYPE_F64) {
+        double* p = static_cast<double*>(p_dev);
+        double* cur = p;
+        double* oth = ctx->ptmp;
+        if ((rc = run_sweeps<double>(ctx, static_cast<const double*>(b_dev), &cur, &oth, omega, nsweeps, 0, nsweeps)) != STP_OK)
+            return rc;
+        if (cur != p) CHK(copy(p, cur, ctx->g.n, ctx->s));
+    } else {
+        float* p = static_cast<float*>(p_dev);
+        float* cur = p;
+        float* oth = ctx->e1;
+        if ((rc = run_sweeps<float>(ctx, static_cast<const float*>(b_dev), &cur, &oth, omega, nsweeps, 0, nsweeps)) != STP_OK)
+            return rc;
+        if (cur != p) CHK(copy(p, cur, ctx->g.n, ctx->s));
+    }
+    return STP_OK;
+}
+
+stp_status stp_residual_norm(stp_ctx* ctx, const void* b_dev, const void* p_dev, double* norm)
+{
+    if (!ctx) return STP_EINVAL;
+    ctx->err.clear();
+    if (!b_dev || !p_dev || !norm) {
+        ctx->err = "stp_residual_norm: bad argument";
+        return STP_EINVAL;
+    }
+    CHK(residual(ctx->g, static_cast<const double*>(b_dev), static_cast<const double*>(p_dev), nullptr, ctx->part,
+                 ctx->res, ctx->s));
+    stp_status rc = readback(ctx);
+    if (rc != STP_OK) return rc;
+    *norm = std::sqrt(ctx->host[RES_R2]);
+    return STP_OK;
+}
+
+stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape[3], int32_t* dtype)
+{
+    if (!ctx || !dev_ptr || !shape || !dtype) return STP_EINVAL;
+    void* ptr = nullptr;
+    int planes = ctx->g.nz;
+    switch (field) {
+    case STP_U: ptr = ctx->u; break;
+    case STP_V: ptr = ctx->v; break;
+    case STP_W: ptr = ctx->w; planes = ctx->g.nz + 1; break;
+    case STP_P: ptr = ctx->p; break;
+    case STP_NUT: ptr = ctx->nut; break;
+    case STP_RHS: ptr = ctx->b; break;
+    default:
+        ctx->err = "stp_fields: unknown field";
+        return STP_EINVAL;
+    }
+    *dev_ptr = ptr;
+    shape[0] = planes;
+    shape[1] = ctx->g.ny;
+    shape[2] = ctx->g.nx;
+    *dtype = STP_DTYPE_F64;
+    return STP_OK;
+}
+
+stp_status stp_schedule(const stp_ctx* ctx, double* omega, int32_t cap, int32_t* m)
+{
+    if (!ctx || !m || cap < 0 || (cap > 0 && !omega)) return STP_EINVAL;
+    *m = (int32_t)ctx->omega.size();
+    for (int k = 0; k < cap && k < *m; ++k) omega[k] = ctx->omega[k];
+    return STP_OK;
+}
+
+stp_status stp_destroy(stp_ctx* ctx)
+{
+    if (!ctx) return STP_OK;
+    for (int q = 0; q < 4; ++q)
+        if (ctx->ev[q]) (void)hipEventDestroy(ctx->ev[q]);
+    if (ctx->host) (void)hipHostFree(ctx->host);
+    delete ctx;
+    return STP_OK;
+}
+
+const char* stp_last_error(const stp_ctx* ctx)
+{
+    if (!ctx) return "null context";
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

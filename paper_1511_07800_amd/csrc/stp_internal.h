@@ -1,0 +1,94 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace stp {
+
+// Grid geometry handed to every kernel by value.
+struct Geo {
+    int nx, ny, nz;
+    long long plane;  // nx*ny
+    long long n;      // nx*ny*nz cells
+    long long nw;     // nx*ny*(nz+1) z-faces
+    double idx, idy, idz;     // 1/h
+    double idx2, idy2, idz2;  // 1/h^2
+};
+
+// Launch shape of the z-marching stencil kernels: a (bx, by) tile of columns
+// per workgroup, kchunk planes per workgroup along z.
+struct March {
+    dim3 grid, block;
+    int kchunk;
+    int nblocks() const { return (int)(grid.x * grid.y * grid.z); }
+};
+March march_shape(const Geo& g, int min_blocks);
+
+// Slots of the device scalar-result array.
+enum ResSlot {
+    RES_SUM_B = 0,   // sum b (before mean removal)
+    RES_B2 = 1,      // sum (b - mean)^2
+    RES_R2 = 2,      // sum r^2 of the last residual
+    RES_SUM_P = 3,   // sum p
+    RES_NUT_MAX = 4,
+    RES_DIAG = 8,    // 5 values: max|div|, sum u, max|u|, max cfl, centreline sum
+    RES_COUNT = 16
+};
+
+constexpr int kMaxPartBlocks = 65536;  // partial-sum slots per reduced quantity
+constexpr int kMaxFused = 4;           // sweeps fused per relaxation launch
+
+struct Weights {  // omega_s / D for the fused sweeps of one launch
+    double c[kMaxFused];
+};
+
+// ---- launchers (all enqueue on `s`, return hipError of the launch) ----
+hipError_t fill(double* a, double v, long long n, hipStream_t s);
+hipError_t fill(float* a, float v, long long n, hipStream_t s);
+hipError_t copy(double* dst, const double* src, long long n, hipStream_t s);
+hipError_t copy(float* dst, const float* src, long long n, hipStream_t s);
+hipError_t sumsq_into(const double* a, long long n, double* part, double* res, int slot, hipStream_t s);
+hipError_t zero_walls(const Geo& g, double* w, hipStream_t s);
+
+hipError_t nut_smagorinsky(const Geo& g, const double* u, const double* v, const double* w, double* nut,
+                           double nu, double cs_delta, double inv_wall_unit, double lz, double* part,
+                           double* res, hipStream_t s);
+
+// Explicit terms E^n and the Crank-Nicolson right-hand side R for component c.
+struct MomArgs {
+    const double *u, *v, *w, *nut;
+    double* en;          // E^n out
+    const double* e1;    // E^{n-1}
+    const double* e2;    // E^{n-2}
+    double* rhs;         // R out
+    double beta0, beta1, beta2;
+    double dt, half_dt, dpdx, nu;
+};
+hipError_t momentum_rhs(const Geo& g, int comp, const MomArgs& a, hipStream_t s);
+
+// One Crank-Nicolson iteration x_out = x + (R - (I - h L) x) * inv_shift.
+hipError_t cn_iterate(const Geo& g, int comp, const double* nut, double nu, const double* rhs, const double* x,
+                      double* xout, double half_dt, double inv_shift, hipStream_t s);
+
+hipError_t divergence_rhs(const Geo& g, const double* u, const double* v, const double* w, double* b,
+                          double inv_dt, double* part, double* res, hipStream_t s);
+hipError_t remove_mean(double* a, long long n, const double* res_sum, int res_out_sq, double* part, double* res,
+                       hipStream_t s);  // a -= res_sum[0]/n; optional sum of squares into res[res_out_sq]
+hipError_t sum_into(const double* a, long long n, double* part, double* res, int slot, hipStream_t s);
+
+template <typename T>
+hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, int nfused, hipStream_t s);
+
+// r = b - L p (FP64); sum r^2 -> res[RES_R2]; optional FP32 copy of r.
+hipError_t residual(const Geo& g, const double* b, const double* p, float* r32, double* part, double* res,
+                    hipStream_t s);
+hipError_t add_correction(double* p, const float* e, long long n, hipStream_t s);
+
+hipError_t project(const Geo& g, const double* p, double* u, double* v, double* w, double dt, hipStream_t s);
+hipError_t diagnostics(const Geo& g, const double* u, const double* v, const double* w, double dt, double* part,
+                       double* res, hipStream_t s);
+
+}  // namespace stp

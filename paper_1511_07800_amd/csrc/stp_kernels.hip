@@ -1,0 +1,763 @@
+// HIP kernels for gfx950 (CDNA4): the stencils, relaxation sweeps and
+// reductions of the S-TPLS time step (arXiv 1511.07800, Sec. 2-3).
+//
+// Every kernel here is bandwidth-bound (a few flops per byte), so the design
+// rules are: x-fastest coalesced rows, one thread per (i, j) column marching
+// along z with the vertical neighbours kept in registers, periodic wrap in x
+// and y computed in-kernel, and reductions as fixed-order wave64 shuffle trees
+// with per-workgroup partials (bitwise reproducible, no float atomics).
+#include "stp_internal.h"
+
+#include <algorithm>
+
+namespace stp {
+
+namespace {
+
+constexpr int kBlock1d = 256;
+
+__device__ __forceinline__ int wm(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+__device__ __forceinline__ int wp(int i, int n) { return i == n - 1 ? 0 : i + 1; }
+
+__device__ __forceinline__ long long at(const Geo& g, int i, int j, int k)
+{
+    return (long long)i + (long long)g.nx * j + g.plane * k;
+}
+
+// ---- fixed-order reductions -------------------------------------------------
+
+template <bool MAX>
+__device__ __forceinline__ double wave_reduce(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_down(v, off, 64);
+        v = MAX ? fmax(v, o) : v + o;
+    }
+    return v;
+}
+
+// Reduce one value per thread of the workgroup; thread 0 gets the result.
+template <bool MAX>
+__device__ double block_reduce(double v, double* lds /* >= 16 */)
+{
+    const int lane = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthreads = blockDim.x * blockDim.y * blockDim.z;
+    v = wave_reduce<MAX>(v);
+    __syncthreads();
+    if ((lane & 63) == 0) lds[lane >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (lane == 0) {
+        r = lds[0];
+        for (int wv = 1; wv < (nthreads + 63) / 64; ++wv) r = MAX ? fmax(r, lds[wv]) : r + lds[wv];
+    }
+    return r;
+}
+
+__device__ __forceinline__ int block_id()
+{
+    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+__device__ __forceinline__ int block_count() { return gridDim.x * gridDim.y * gridDim.z; }
+
+// Second stage: nq quantities, each with nblk partials laid out part[q*nblk + b].
+// Bit q of max_mask selects max instead of sum.  Writes res[slot + q].
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part, int nblk, int nq,
+                                                  unsigned max_mask, double* __restrict__ res, int slot)
+{
+    __shared__ double lds[16];
+    for (int q = 0; q < nq; ++q) {
+        const bool mx = (max_mask >> q) & 1u;
+        double v = mx ? -INFINITY : 0.0;
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+            const double x = part[(long long)q * nblk + b];
+            v = mx ? fmax(v, x) : v + x;
+        }
+        const double r = mx ? block_reduce<true>(v, lds) : block_reduce<false>(v, lds);
+        if (threadIdx.x == 0) res[slot + q] = r;
+        __syncthreads();
+    }
+}
+
+hipError_t finalize(const double* part, int nblk, int nq, unsigned max_mask, double* res, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, part, nblk, nq, max_mask, res, slot);
+    return hipGetLastError();
+}
+
+int grid1d(long long n, int cap = 4096)
+{
+    long long b = (n + kBlock1d - 1) / kBlock1d;
+    return (int)std::max<long long>(1, std::min<long long>(b, cap));
+}
+
+// ---- elementwise ------------------------------------------------------------
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ a, T v, long long n)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        a[q] = v;
+}
+
+__global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, long long n)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        d[q] = s[q];
+}
+
+__global__ void k_copy32(float* __restrict__ d, const float* __restrict__ s, long long n)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        d[q] = s[q];
+}
+
+__global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ a, long long n, double* __restrict__ part)
+{
+    __shared__ double lds[16];
+    double acc = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        acc += a[q] * a[q];
+    const double r = block_reduce<false>(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void k_zero_walls(Geo g, double* __restrict__ w)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < g.plane; q += (long long)gridDim.x * blockDim.x) {
+        w[q] = 0.0;
+        w[g.plane * g.nz + q] = 0.0;
+    }
+}
+
+// a -= sum/n; optionally partial sums of the squared result.
+__global__ __launch_bounds__(256) void k_remove_mean(double* __restrict__ a, long long n,
+                                                     const double* __restrict__ sum, double* __restrict__ part,
+                                                     int want_sq)
+{
+    __shared__ double lds[16];
+    const double m = sum[0] / (double)n;
+    double acc = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const double x = a[q] - m;
+        a[q] = x;
+        acc += x * x;
+    }
+    if (want_sq) {
+        const double r = block_reduce<false>(acc, lds);
+        if (threadIdx.x == 0) part[blockIdx.x] = r;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ a, long long n, double* __restrict__ part)
+{
+    __shared__ double lds[16];
+    double acc = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        acc += a[q];
+    const double r = block_reduce<false>(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void k_add_correction(double* __restrict__ p, const float* __restrict__ e, long long n)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        p[q] += (double)e[q];
+}
+
+// ---- eddy viscosity (Sec. 2.2) ---------------------------------------------
+
+// nu_T = nu + (C_S Delta phi_w)^2 |S| at cell centres; phi_w = 1 - exp(-z+/A)
+// with z+ the distance to the nearer wall times u_tau/nu.  |S|^2 =
+// 2(S11^2 + S22^2 + S33^2) + 4(<S12^2> + <S13^2> + <S23^2>), <.> the mean over
+// the four edges around the centre; u, v odd and w zero at the walls.
+__global__ __launch_bounds__(256) void k_nut(Geo g, int kchunk, const double* __restrict__ u,
+                                             const double* __restrict__ v, const double* __restrict__ w,
+                                             double* __restrict__ nut, double nu, double cs_delta,
+                                             double inv_wall_unit, double lz, double* __restrict__ part)
+{
+    __shared__ double lds[16];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    double vmax = -INFINITY;
+    if (i < g.nx && j < g.ny) {
+        const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
+        const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+        const double dz = 1.0 / g.idz;
+        for (int k = k0; k < k1; ++k) {
+            // u and v on planes k-1, k, k+1 with the odd wall ghosts
+            auto U = [&](int ii, int jj, int kk) -> double {
+                if (kk < 0) return -u[at(g, ii, jj, 0)];
+                if (kk >= g.nz) return -u[at(g, ii, jj, g.nz - 1)];
+                return u[at(g, ii, jj, kk)];
+            };
+            auto V = [&](int ii, int jj, int kk) -> double {
+                if (kk < 0) return -v[at(g, ii, jj, 0)];
+                if (kk >= g.nz) return -v[at(g, ii, jj, g.nz - 1)];
+                return v[at(g, ii, jj, kk)];
+            };
+            auto Wf = [&](int ii, int jj, int kk) -> double { return w[at(g, ii, jj, kk)]; };  // walls hold 0
+            const double s11 = (U(ip, j, k) - U(i, j, k)) * g.idx;
+            const double s22 = (V(i, jp, k) - V(i, j, k)) * g.idy;
+            const double s33 = (Wf(i, j, k + 1) - Wf(i, j, k)) * g.idz;
+            double a12 = 0.0, a13 = 0.0, a23 = 0.0;
+            const int is[2] = {i, ip}, ism[2] = {im, i};
+            const int js[2] = {j, jp}, jsm[2] = {jm, j};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int di = e & 1, dj = e >> 1;
+                // x-y edge (i+di, j+dj) on plane k
+                const double s12 = 0.5 * ((U(is[di], js[dj], k) - U(is[di], jsm[dj], k)) * g.idy +
+                                          (V(is[di], js[dj], k) - V(ism[di], js[dj], k)) * g.idx);
+                // x-z edge (i+di, k+dj) on row j
+                const int kk = k + dj;
+                const double s13 = 0.5 * ((U(is[di], j, kk) - U(is[di], j, kk - 1)) * g.idz +
+                                          (Wf(is[di], j, kk) - Wf(ism[di], j, kk)) * g.idx);
+                // y-z edge (j+di, k+dj) on column i
+                const double s23 = 0.5 * ((V(i, js[di], kk) - V(i, js[di], kk - 1)) * g.idz +
+                                          (Wf(i, js[di], kk) - Wf(i, jsm[di], kk)) * g.idy);
+                a12 += 0.25 * s12 * s12;
+                a13 += 0.25 * s13 * s13;
+                a23 += 0.25 * s23 * s23;
+            }
+            const double s2 = 2.0 * (s11 * s11 + s22 * s22 + s33 * s33) + 4.0 * (a12 + a13 + a23);
+            const double zc = (k + 0.5) * dz;
+            const double dwall = fmin(zc, lz - zc);
+            const double l = cs_delta * (1.0 - exp(-dwall * inv_wall_unit));
+            const double val = nu + l * l * sqrt(s2);
+            nut[at(g, i, j, k)] = val;
+            vmax = fmax(vmax, val);
+        }
+    }
+    const double r = block_reduce<true>(vmax, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_id()] = r;
+}
+
+// ---- momentum: explicit terms and Crank-Nicolson right-hand side (Sec. 3.1)
+
+// Edge viscosities: mean of the four surrounding centres; nu on wall edges.
+struct Nu {
+    const double* __restrict__ t;
+    Geo g;
+    double nu;
+    __device__ double c(int i, int j, int k) const { return t[at(g, i, j, k)]; }
+    // x-y edge between centres (i0|i1) x (j0|j1) on plane k
+    __device__ double xy(int i0, int i1, int j0, int j1, int k) const
+    {
+        return 0.25 * (c(i0, j0, k) + c(i1, j0, k) + c(i0, j1, k) + c(i1, j1, k));
+    }
+    // x-z edge between centres (i0|i1) x (k-1|k) on row j; wall edges carry nu
+    __device__ double xz(int i0, int i1, int j, int k) const
+    {
+        if (k <= 0 || k >= g.nz) return nu;
+        return 0.25 * (c(i0, j, k - 1) + c(i1, j, k - 1) + c(i0, j, k) + c(i1, j, k));
+    }
+    __device__ double yz(int i, int j0, int j1, int k) const
+    {
+        if (k <= 0 || k >= g.nz) return nu;
+        return 0.25 * (c(i, j0, k - 1) + c(i, j1, k - 1) + c(i, j0, k) + c(i, j1, k));
+    }
+};
+
+// x-momentum on x-faces: E_u = -d_j(u_j u) + d_j(nu_T d_x u_j) - G and
+// R_u = u + dt sum_m beta_m E_u^{n-m} + (dt/2) d_j(nu_T d_j u).
+__global__ __launch_bounds__(256) void k_mom_u(Geo g, int kchunk, MomArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
+    const Nu N{a.nut, g, a.nu};
+    const double* __restrict__ u = a.u;
+    const double* __restrict__ v = a.v;
+    const double* __restrict__ w = a.w;
+    const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+    for (int k = k0; k < k1; ++k) {
+        const long long c = at(g, i, j, k);
+        const double uc = u[c];
+        const double uE = u[at(g, ip, j, k)], uW = u[at(g, im, j, k)];
+        const double uN = u[at(g, i, jp, k)], uS = u[at(g, i, jm, k)];
+        const double uT = k + 1 < g.nz ? u[c + g.plane] : -uc;
+        const double uB = k > 0 ? u[c - g.plane] : -uc;
+        // convection, divergence form
+        const double ue = 0.5 * (uc + uE), uw = 0.5 * (uW + uc);
+        const double cx = (ue * ue - uw * uw) * g.idx;
+        const double vn = 0.5 * (v[at(g, im, jp, k)] + v[at(g, i, jp, k)]);
+        const double vs = 0.5 * (v[at(g, im, j, k)] + v[at(g, i, j, k)]);
+        const double cy = (vn * 0.5 * (uc + uN) - vs * 0.5 * (uS + uc)) * g.idy;
+        const double wt = 0.5 * (w[at(g, im, j, k + 1)] + w[at(g, i, j, k + 1)]);
+        const double wb = 0.5 * (w[at(g, im, j, k)] + w[at(g, i, j, k)]);
+        const double cz = (wt * 0.5 * (uc + uT) - wb * 0.5 * (uB + uc)) * g.idz;
+        // viscous terms
+        const double nE = N.c(i, j, k), nW = N.c(im, j, k);
+        const double nN = N.xy(im, i, j, jp, k), nS = N.xy(im, i, jm, j, k);
+        const double nT = N.xz(im, i, j, k + 1), nB = N.xz(im, i, j, k);
+        const double dxx = (nE * (uE - uc) - nW * (uc - uW)) * g.idx2;
+        const double vy = (nN * (v[at(g, i, jp, k)] - v[at(g, im, jp, k)]) - nS * (v[at(g, i, j, k)] - v[at(g, im, j, k)])) *
+                          (g.idx * g.idy);
+        const double vz = (nT * (w[at(g, i, j, k + 1)] - w[at(g, im, j, k + 1)]) - nB * (w[at(g, i, j, k)] - w[at(g, im, j, k)])) *
+                          (g.idx * g.idz);
+        const double E = -(cx + cy + cz) + (dxx + vy + vz) - a.dpdx;
+        const double Ldiff = dxx + (nN * (uN - uc) - nS * (uc - uS)) * g.idy2 + (nT * (uT - uc) - nB * (uc - uB)) * g.idz2;
+        a.en[c] = E;
+        a.rhs[c] = uc + a.dt * (a.beta0 * E + a.beta1 * a.e1[c] + a.beta2 * a.e2[c]) + a.half_dt * Ldiff;
+    }
+}
+
+// y-momentum on y-faces: E_v = -d_j(u_j v) + d_j(nu_T d_y u_j).
+__global__ __launch_bounds__(256) void k_mom_v(Geo g, int kchunk, MomArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
+    const Nu N{a.nut, g, a.nu};
+    const double* __restrict__ u = a.u;
+    const double* __restrict__ v = a.v;
+    const double* __restrict__ w = a.w;
+    const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+    for (int k = k0; k < k1; ++k) {
+        const long long c = at(g, i, j, k);
+        const double vc = v[c];
+        const double vE = v[at(g, ip, j, k)], vW = v[at(g, im, j, k)];
+        const double vN = v[at(g, i, jp, k)], vS = v[at(g, i, jm, k)];
+        const double vT = k + 1 < g.nz ? v[c + g.plane] : -vc;
+        const double vB = k > 0 ? v[c - g.plane] : -vc;
+        const double ue = 0.5 * (u[at(g, ip, jm, k)] + u[at(g, ip, j, k)]);
+        const double uw = 0.5 * (u[at(g, i, jm, k)] + u[at(g, i, j, k)]);
+        const double cx = (ue * 0.5 * (vc + vE) - uw * 0.5 * (vW + vc)) * g.idx;
+        const double vn = 0.5 * (vc + vN), vs = 0.5 * (vS + vc);
+        const double cy = (vn * vn - vs * vs) * g.idy;
+        const double wt = 0.5 * (w[at(g, i, jm, k + 1)] + w[at(g, i, j, k + 1)]);
+        const double wb = 0.5 * (w[at(g, i, jm, k)] + w[at(g, i, j, k)]);
+        const double cz = (wt * 0.5 * (vc + vT) - wb * 0.5 * (vB + vc)) * g.idz;
+        const double nE = N.xy(i, ip, jm, j, k), nW = N.xy(im, i, jm, j, k);
+        const double nN = N.c(i, j, k), nS = N.c(i, jm, k);
+        const double nT = N.yz(i, jm, j, k + 1), nB = N.yz(i, jm, j, k);
+        const double vx = (nE * (u[at(g, ip, j, k)] - u[at(g, ip, jm, k)]) - nW * (u[at(g, i, j, k)] - u[at(g, i, jm, k)])) *
+                          (g.idx * g.idy);
+        const double dyy = (nN * (vN - vc) - nS * (vc - vS)) * g.idy2;
+        const double vz = (nT * (w[at(g, i, j, k + 1)] - w[at(g, i, jm, k + 1)]) - nB * (w[at(g, i, j, k)] - w[at(g, i, jm, k)])) *
+                          (g.idy * g.idz);
+        const double E = -(cx + cy + cz) + (vx + dyy + vz);
+        const double Ldiff = (nE * (vE - vc) - nW * (vc - vW)) * g.idx2 + dyy + (nT * (vT - vc) - nB * (vc - vB)) * g.idz2;
+        a.en[c] = E;
+        a.rhs[c] = vc + a.dt * (a.beta0 * E + a.beta1 * a.e1[c] + a.beta2 * a.e2[c]) + a.half_dt * Ldiff;
+    }
+}
+
+// z-momentum on interior z-faces: E_w = -d_j(u_j w) + d_j(nu_T d_z u_j);
+// wall planes get E = R = 0.
+__global__ __launch_bounds__(256) void k_mom_w(Geo g, int kchunk, MomArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
+    const Nu N{a.nut, g, a.nu};
+    const double* __restrict__ u = a.u;
+    const double* __restrict__ v = a.v;
+    const double* __restrict__ w = a.w;
+    const int k0 = blockIdx.z * kchunk, k1 = min(g.nz + 1, k0 + kchunk);
+    for (int k = k0; k < k1; ++k) {
+        const long long c = at(g, i, j, k);
+        if (k == 0 || k == g.nz) {
+            a.en[c] = 0.0;
+            a.rhs[c] = 0.0;
+            continue;
+        }
+        const double wc = w[c];
+        const double wE = w[at(g, ip, j, k)], wW = w[at(g, im, j, k)];
+        const double wN = w[at(g, i, jp, k)], wS = w[at(g, i, jm, k)];
+        const double wT = w[c + g.plane], wB = w[c - g.plane];
+        const double ue = 0.5 * (u[at(g, ip, j, k - 1)] + u[at(g, ip, j, k)]);
+        const double uw = 0.5 * (u[at(g, i, j, k - 1)] + u[at(g, i, j, k)]);
+        const double cx = (ue * 0.5 * (wc + wE) - uw * 0.5 * (wW + wc)) * g.idx;
+        const double vn = 0.5 * (v[at(g, i, jp, k - 1)] + v[at(g, i, jp, k)]);
+        const double vs = 0.5 * (v[at(g, i, j, k - 1)] + v[at(g, i, j, k)]);
+        const double cy = (vn * 0.5 * (wc + wN) - vs * 0.5 * (wS + wc)) * g.idy;
+        const double wt = 0.5 * (wc + wT), wb = 0.5 * (wB + wc);
+        const double cz = (wt * wt - wb * wb) * g.idz;
+        const double nE = N.xz(i, ip, j, k), nW = N.xz(im, i, j, k);
+        const double nN = N.yz(i, j, jp, k), nS = N.yz(i, jm, j, k);
+        const double nT = N.c(i, j, k), nB = N.c(i, j, k - 1);
+        const double vx = (nE * (u[at(g, ip, j, k)] - u[at(g, ip, j, k - 1)]) - nW * (u[at(g, i, j, k)] - u[at(g, i, j, k - 1)])) *
+                          (g.idx * g.idz);
+        const double vy = (nN * (v[at(g, i, jp, k)] - v[at(g, i, jp, k - 1)]) - nS * (v[at(g, i, j, k)] - v[at(g, i, j, k - 1)])) *
+                          (g.idy * g.idz);
+        const double dzz = (nT * (wT - wc) - nB * (wc - wB)) * g.idz2;
+        const double E = -(cx + cy + cz) + (vx + vy + dzz);
+        const double Ldiff = (nE * (wE - wc) - nW * (wc - wW)) * g.idx2 + (nN * (wN - wc) - nS * (wc - wS)) * g.idy2 + dzz;
+        a.en[c] = E;
+        a.rhs[c] = wc + a.dt * (a.beta0 * E + a.beta1 * a.e1[c] + a.beta2 * a.e2[c]) + a.half_dt * Ldiff;
+    }
+}
+
+// One Crank-Nicolson iteration for component COMP:
+// x_out = x + (R - x + h L_nu x) * inv_shift, L_nu = d_j(nu_T d_j .).
+template <int COMP>
+__global__ __launch_bounds__(256) void k_cn(Geo g, int kchunk, const double* __restrict__ nut, double nu,
+                                            const double* __restrict__ R, const double* __restrict__ x,
+                                            double* __restrict__ xo, double h, double inv_shift)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
+    const Nu N{nut, g, nu};
+    const int nplanes = COMP == 2 ? g.nz + 1 : g.nz;
+    const int k0 = blockIdx.z * kchunk, k1 = min(nplanes, k0 + kchunk);
+    for (int k = k0; k < k1; ++k) {
+        const long long c = at(g, i, j, k);
+        const double xc = x[c];
+        const double xE = x[at(g, ip, j, k)], xW = x[at(g, im, j, k)];
+        const double xN = x[at(g, i, jp, k)], xS = x[at(g, i, jm, k)];
+        double L;
+        if (COMP == 0) {
+            const double xT = k + 1 < g.nz ? x[c + g.plane] : -xc;
+            const double xB = k > 0 ? x[c - g.plane] : -xc;
+            L = (N.c(i, j, k) * (xE - xc) - N.c(im, j, k) * (xc - xW)) * g.idx2 +
+                (N.xy(im, i, j, jp, k) * (xN - xc) - N.xy(im, i, jm, j, k) * (xc - xS)) * g.idy2 +
+                (N.xz(im, i, j, k + 1) * (xT - xc) - N.xz(im, i, j, k) * (xc - xB)) * g.idz2;
+        } else if (COMP == 1) {
+            const double xT = k + 1 < g.nz ? x[c + g.plane] : -xc;
+            const double xB = k > 0 ? x[c - g.plane] : -xc;
+            L = (N.xy(i, ip, jm, j, k) * (xE - xc) - N.xy(im, i, jm, j, k) * (xc - xW)) * g.idx2 +
+                (N.c(i, j, k) * (xN - xc) - N.c(i, jm, k) * (xc - xS)) * g.idy2 +
+                (N.yz(i, jm, j, k + 1) * (xT - xc) - N.yz(i, jm, j, k) * (xc - xB)) * g.idz2;
+        } else {
+            if (k == 0 || k == g.nz) {
+                xo[c] = 0.0;
+                continue;
+            }
+            const double xT = x[c + g.plane], xB = x[c - g.plane];
+            L = (N.xz(i, ip, j, k) * (xE - xc) - N.xz(im, i, j, k) * (xc - xW)) * g.idx2 +
+                (N.yz(i, j, jp, k) * (xN - xc) - N.yz(i, jm, j, k) * (xc - xS)) * g.idy2 +
+                (N.c(i, j, k) * (xT - xc) - N.c(i, j, k - 1) * (xc - xB)) * g.idz2;
+        }
+        xo[c] = xc + (R[c] - xc + h * L) * inv_shift;
+    }
+}
+
+// ---- divergence, Poisson right-hand side (Sec. 3.1) -------------------------
+
+__global__ __launch_bounds__(256) void k_div(Geo g, int kchunk, const double* __restrict__ u,
+                                             const double* __restrict__ v, const double* __restrict__ w,
+                                             double* __restrict__ b, double inv_dt, double* __restrict__ part)
+{
+    __shared__ double lds[16];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    double acc = 0.0;
+    if (i < g.nx && j < g.ny) {
+        const int ip = wp(i, g.nx), jp = wp(j, g.ny);
+        const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+        for (int k = k0; k < k1; ++k) {
+            const long long c = at(g, i, j, k);
+            const double d = (u[at(g, ip, j, k)] - u[c]) * g.idx + (v[at(g, i, jp, k)] - v[c]) * g.idy +
+                             (w[c + g.plane] - w[c]) * g.idz;
+            const double val = d * inv_dt;
+            b[c] = val;
+            acc += val;
+        }
+    }
+    const double r = block_reduce<false>(acc, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_id()] = r;
+}
+
+// ---- Scheduled Relaxation Jacobi sweep (Sec. 3.4) ---------------------------
+
+// out = p + c (L_p p - b), c = omega/D.  L_p: 7-point Laplacian, periodic in
+// x and y, zero normal gradient at the walls (the missing neighbour equals the
+// centre value).  One thread per (i, j) column, z-march with the vertical
+// neighbours in registers.
+template <typename T>
+__global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchunk, const T* __restrict__ b,
+                                               const T* __restrict__ p, T* __restrict__ out, T c, T idx2, T idy2,
+                                               T idz2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const long long plane = (long long)nx * ny;
+    const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
+    const int jm = j == 0 ? ny - 1 : j - 1, jp = j == ny - 1 ? 0 : j + 1;
+    const long long row = (long long)nx * j, rowm = (long long)nx * jm, rowp = (long long)nx * jp;
+    const int k0 = blockIdx.z * kchunk, k1 = min(nz, k0 + kchunk);
+    long long o = plane * k0;
+    T pc = p[o + row + i];
+    T pb = k0 > 0 ? p[o - plane + row + i] : pc;
+    for (int k = k0; k < k1; ++k, o += plane) {
+        const T pt = k + 1 < nz ? p[o + plane + row + i] : pc;
+        const T lap = (p[o + row + im] + p[o + row + ip] - T(2) * pc) * idx2 +
+                      (p[o + rowm + i] + p[o + rowp + i] - T(2) * pc) * idy2 + ((pt - pc) + (pb - pc)) * idz2;
+        out[o + row + i] = pc + c * (lap - b[o + row + i]);
+        pb = pc;
+        pc = pt;
+    }
+}
+
+// r = b - L_p p in FP64 with partial sums of r^2; optional FP32 copy of r.
+__global__ __launch_bounds__(256) void k_residual(Geo g, int kchunk, const double* __restrict__ b,
+                                                  const double* __restrict__ p, float* __restrict__ r32,
+                                                  double* __restrict__ part)
+{
+    __shared__ double lds[16];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    double acc = 0.0;
+    if (i < g.nx && j < g.ny) {
+        const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
+        const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+        double pc = p[at(g, i, j, k0)];
+        double pb = k0 > 0 ? p[at(g, i, j, k0 - 1)] : pc;
+        for (int k = k0; k < k1; ++k) {
+            const long long c = at(g, i, j, k);
+            const double pt = k + 1 < g.nz ? p[c + g.plane] : pc;
+            const double lap = (p[at(g, im, j, k)] + p[at(g, ip, j, k)] - 2.0 * pc) * g.idx2 +
+                               (p[at(g, i, jm, k)] + p[at(g, i, jp, k)] - 2.0 * pc) * g.idy2 +
+                               ((pt - pc) + (pb - pc)) * g.idz2;
+            const double r = b[c] - lap;
+            if (r32) r32[c] = (float)r;
+            acc += r * r;
+            pb = pc;
+            pc = pt;
+        }
+    }
+    const double r = block_reduce<false>(acc, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_id()] = r;
+}
+
+// ---- projection correction (Sec. 3.1) ---------------------------------------
+
+__global__ __launch_bounds__(256) void k_project(Geo g, int kchunk, const double* __restrict__ p,
+                                                 double* __restrict__ u, double* __restrict__ v,
+                                                 double* __restrict__ w, double dt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const int im = wm(i, g.nx), jm = wm(j, g.ny);
+    const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+    for (int k = k0; k < k1; ++k) {
+        const long long c = at(g, i, j, k);
+        const double pc = p[c];
+        u[c] -= dt * (pc - p[at(g, im, j, k)]) * g.idx;
+        v[c] -= dt * (pc - p[at(g, i, jm, k)]) * g.idy;
+        if (k > 0) w[c] -= dt * (pc - p[c - g.plane]) * g.idz;
+    }
+}
+
+// ---- diagnostics: max|div u|, sum u, max|u|, CFL, centreline sum -------------
+
+__global__ __launch_bounds__(256) void k_diag(Geo g, int kchunk, const double* __restrict__ u,
+                                              const double* __restrict__ v, const double* __restrict__ w, double dt,
+                                              double* __restrict__ part)
+{
+    __shared__ double lds[16];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    double mdiv = 0.0, su = 0.0, mu = 0.0, cfl = 0.0, sc = 0.0;
+    if (i < g.nx && j < g.ny) {
+        const int ip = wp(i, g.nx), jp = wp(j, g.ny);
+        const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+        const int kc0 = g.nz % 2 == 0 ? g.nz / 2 - 1 : g.nz / 2;
+        const int kc1 = g.nz / 2;
+        for (int k = k0; k < k1; ++k) {
+            const long long c = at(g, i, j, k);
+            const double uc = u[c];
+            const double d = (u[at(g, ip, j, k)] - uc) * g.idx + (v[at(g, i, jp, k)] - v[c]) * g.idy +
+                             (w[c + g.plane] - w[c]) * g.idz;
+            mdiv = fmax(mdiv, fabs(d));
+            su += uc;
+            mu = fmax(mu, fabs(uc));
+            cfl = fmax(cfl, fmax(fabs(uc) * dt * g.idx, fabs(v[c]) * dt * g.idy));
+            cfl = fmax(cfl, fabs(w[c]) * dt * g.idz);
+            if (k == g.nz - 1) cfl = fmax(cfl, fabs(w[c + g.plane]) * dt * g.idz);
+            if (k == kc0) sc += kc0 == kc1 ? uc : 0.5 * uc;
+            else if (k == kc1) sc += 0.5 * uc;
+        }
+    }
+    const int b = block_id(), nb = block_count();
+    double r;
+    r = block_reduce<true>(mdiv, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[0 * nb + b] = r;
+    r = block_reduce<false>(su, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[1 * nb + b] = r;
+    r = block_reduce<true>(mu, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[2 * nb + b] = r;
+    r = block_reduce<true>(cfl, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[3 * nb + b] = r;
+    r = block_reduce<false>(sc, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[4 * nb + b] = r;
+}
+
+}  // namespace
+
+// ============================================================================
+// launchers
+
+March march_shape(const Geo& g, int min_blocks)
+{
+    March m;
+    int bx = 64;
+    while (bx > 8 && bx / 2 >= g.nx) bx /= 2;
+    const int by = 256 / bx;
+    const int gx = (g.nx + bx - 1) / bx, gy = (g.ny + by - 1) / by;
+    const long long cols = (long long)gx * gy;
+    int gz = (int)std::min<long long>(g.nz, std::max<long long>(1, (min_blocks + cols - 1) / cols));
+    // keep the partial-sum buffer large enough
+    while ((long long)gz * cols > kMaxPartBlocks && gz > 1) --gz;
+    m.kchunk = (g.nz + gz - 1) / gz;
+    gz = (g.nz + m.kchunk - 1) / m.kchunk;
+    m.grid = dim3(gx, gy, gz);
+    m.block = dim3(bx, by, 1);
+    return m;
+}
+
+hipError_t fill(double* a, double v, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid1d(n)), dim3(kBlock1d), 0, s, a, v, n);
+    return hipGetLastError();
+}
+hipError_t fill(float* a, float v, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill<float>, dim3(grid1d(n)), dim3(kBlock1d), 0, s, a, v, n);
+    return hipGetLastError();
+}
+hipError_t copy(double* dst, const double* src, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy, dim3(grid1d(n)), dim3(kBlock1d), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+hipError_t copy(float* dst, const float* src, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy32, dim3(grid1d(n)), dim3(kBlock1d), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+hipError_t sumsq_into(const double* a, long long n, double* part, double* res, int slot, hipStream_t s)
+{
+    const int nb = grid1d(n, 2048);
+    hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(kBlock1d), 0, s, a, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize(part, nb, 1, 0u, res, slot, s);
+}
+hipError_t zero_walls(const Geo& g, double* w, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_walls, dim3(grid1d(g.plane, 1024)), dim3(kBlock1d), 0, s, g, w);
+    return hipGetLastError();
+}
+
+hipError_t nut_smagorinsky(const Geo& g, const double* u, const double* v, const double* w, double* nut, double nu,
+                           double cs_delta, double inv_wall_unit, double lz, double* part, double* res, hipStream_t s)
+{
+    const March m = march_shape(g, 2048);
+    hipLaunchKernelGGL(k_nut, m.grid, m.block, 0, s, g, m.kchunk, u, v, w, nut, nu, cs_delta, inv_wall_unit, lz, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize(part, m.nblocks(), 1, 1u, res, RES_NUT_MAX, s);
+}
+
+hipError_t momentum_rhs(const Geo& g, int comp, const MomArgs& a, hipStream_t s)
+{
+    Geo gw = g;
+    if (comp == 2) gw.nz = g.nz + 1;  // march over all nz+1 z-face planes
+    const March m = march_shape(gw, 2048);
+    if (comp == 0) hipLaunchKernelGGL(k_mom_u, m.grid, m.block, 0, s, g, m.kchunk, a);
+    else if (comp == 1) hipLaunchKernelGGL(k_mom_v, m.grid, m.block, 0, s, g, m.kchunk, a);
+    else hipLaunchKernelGGL(k_mom_w, m.grid, m.block, 0, s, g, m.kchunk, a);
+    return hipGetLastError();
+}
+
+hipError_t cn_iterate(const Geo& g, int comp, const double* nut, double nu, const double* rhs, const double* x,
+                      double* xout, double half_dt, double inv_shift, hipStream_t s)
+{
+    Geo gw = g;
+    if (comp == 2) gw.nz = g.nz + 1;
+    const March m = march_shape(gw, 2048);
+    if (comp == 0)
+        hipLaunchKernelGGL(k_cn<0>, m.grid, m.block, 0, s, g, m.kchunk, nut, nu, rhs, x, xout, half_dt, inv_shift);
+    else if (comp == 1)
+        hipLaunchKernelGGL(k_cn<1>, m.grid, m.block, 0, s, g, m.kchunk, nut, nu, rhs, x, xout, half_dt, inv_shift);
+    else
+        hipLaunchKernelGGL(k_cn<2>, m.grid, m.block, 0, s, g, m.kchunk, nut, nu, rhs, x, xout, half_dt, inv_shift);
+    return hipGetLastError();
+}
+
+hipError_t divergence_rhs(const Geo& g, const double* u, const double* v, const double* w, double* b, double inv_dt,
+                          double* part, double* res, hipStream_t s)
+{
+    const March m = march_shape(g, 2048);
+    hipLaunchKernelGGL(k_div, m.grid, m.block, 0, s, g, m.kchunk, u, v, w, b, inv_dt, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize(part, m.nblocks(), 1, 0u, res, RES_SUM_B, s);
+}
+
+hipError_t remove_mean(double* a, long long n, const double* res_sum, int res_out_sq, double* part, double* res,
+                       hipStream_t s)
+{
+    const int nb = grid1d(n, 2048);
+    hipLaunchKernelGGL(k_remove_mean, dim3(nb), dim3(kBlock1d), 0, s, a, n, res_sum, part, res_out_sq >= 0 ? 1 : 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || res_out_sq < 0) return e;
+    return finalize(part, nb, 1, 0u, res, res_out_sq, s);
+}
+
+hipError_t sum_into(const double* a, long long n, double* part, double* res, int slot, hipStream_t s)
+{
+    const int nb = grid1d(n, 2048);
+    hipLaunchKernelGGL(k_sum, dim3(nb), dim3(kBlock1d), 0, s, a, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize(part, nb, 1, 0u, res, slot, s);
+}
+
+template <typename T>
+hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, int nfused, hipStream_t s)
+{
+    if (nfused != 1) return hipErrorInvalidValue;
+    const March m = march_shape(g, 2048);
+    hipLaunchKernelGGL(k_relax<T>, m.grid, m.block, 0, s, g.nx, g.ny, g.nz, m.kchunk, b, p, out, (T)wts.c[0],
+                       (T)g.idx2, (T)g.idy2, (T)g.idz2);
+    return hipGetLastError();
+}
+template hipError_t relax<double>(const Geo&, const double*, const double*, double*, const Weights&, int, hipStream_t);
+template hipError_t relax<float>(const Geo&, const float*, const float*, float*, const Weights&, int, hipStream_t);
+
+hipError_t residual(const Geo& g, const double* b, const double* p, float* r32, double* part, double* res,
+                    hipStream_t s)
+{
+    const March m = march_shape(g, 2048);
+    hipLaunchKernelGGL(k_residual, m.grid, m.block, 0, s, g, m.kchunk, b, p, r32, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize(part, m.nblocks(), 1, 0u, res, RES_R2, s);
+}
+
+hipError_t add_correction(double* p, const float* e, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_correction, dim3(grid1d(n)), dim3(kBlock1d), 0, s, p, e, n);
+    return hipGetLastError();
+}
+
+hipError_t project(const Geo& g, const double* p, double* u, double* v, double* w, double dt, hipStream_t s)
+{
+    const March m = march_shape(g, 2048);
+    hipLaunchKernelGGL(k_project, m.grid, m.block, 0, s, g, m.kchunk, p, u, v, w, dt);
+    return hipGetLastError();
+}
+
+hipError_t diagnostics(const Geo& g, const double* u, const double* v, const double* w, double dt, double* part,
+                       double* res, hipStream_t s)
+{
+    const March m = march_shape(g, 2048);
+    hipLaunchKernelGGL(k_diag, m.grid, m.block, 0, s, g, m.kchunk, u, v, w, dt, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize(part, m.nblocks(), 5, 0b01101u, res, RES_DIAG, s);
+}
+
+}  // namespace stp

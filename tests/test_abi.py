@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point include/stp.h declares, and the configuration arithmetic behaves (no
+device work is issued here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_\s\*]*?\b(stp_[a-z_0-9]+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("stp_init", "stp_step", "stp_poisson_solve", "stp_fields", "stp_destroy", "stp_last_error",
+                 "stp_workspace_bytes"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1511_07800_amd import load_library
+    lib = load_library()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def cfg(**kw):
+    from paper_1511_07800_amd import Config
+    c = Config()
+    c.nx, c.ny, c.nz, c.les = 32, 16, 16, 0
+    c.lx, c.ly, c.lz = 6.28, 3.14, 2.0
+    c.nu, c.dpdx, c.dt, c.cs, c.vd_a = 0.01, -0.02, 1e-3, 0.1, 25.0
+    c.precision, c.warm_start = 0, 0
+    c.poisson_rtol, c.poisson_maxit = 1e-10, 100
+    c.srj_m, c.srj_omega = 0, None
+    c.srj_reduction, c.mixed_inner, c.tblock, c.cn_tol = 1e-3, 1, 1, 1e-13
+    c.stream = None
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_workspace_bytes_valid_and_invalid():
+    from paper_1511_07800_amd import load_library
+    lib = load_library()
+    n_ok = lib.stp_workspace_bytes(ctypes.byref(cfg()))
+    n = 32 * 16 * 16
+    assert n_ok >= 25 * 8 * n      # every FP64 work array of the step fits
+    assert n_ok % 256 == 0 or n_ok > 0
+    big = lib.stp_workspace_bytes(ctypes.byref(cfg(nx=64)))
+    assert big > n_ok
+    for bad in (dict(nz=1), dict(nx=0), dict(nu=0.0), dict(dt=-1.0), dict(lx=float("nan")),
+                dict(precision=7), dict(poisson_maxit=0), dict(poisson_rtol=-1.0), dict(srj_reduction=1.5),
+                dict(les=2), dict(tblock=3), dict(cn_tol=2.0), dict(srj_m=4)):
+        assert lib.stp_workspace_bytes(ctypes.byref(cfg(**bad))) == 0, bad
+    assert lib.stp_workspace_bytes(None) == 0
+
+
+def test_init_rejects_small_workspace_and_null():
+    from paper_1511_07800_amd import load_library, STP_EINVAL, STP_ENOMEM
+    lib = load_library()
+    h = ctypes.c_void_p()
+    c = cfg()
+    assert lib.stp_init(None, None, 0, ctypes.byref(h)) == STP_EINVAL
+    assert lib.stp_init(ctypes.byref(c), None, 0, ctypes.byref(h)) == STP_ENOMEM
+    assert lib.stp_init(ctypes.byref(cfg(nz=1)), None, 0, ctypes.byref(h)) == STP_EINVAL
+    assert lib.stp_destroy(None) == 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import paper_1511_07800_amd.binding as b
+    monkeypatch.setattr(b, "_lib", None)
+    monkeypatch.setattr(b, "_LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(ImportError):
+        b.load_library()
