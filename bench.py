@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--sweeps", type=int, default=200, help="sweeps in the kernel roofline timing")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only run a plain copy of known size and the relaxation kernels (for rocprofv3 counters)")
     return ap.parse_args()
 
 
@@ -54,58 +56,88 @@ def make_channel(wl, precision, rtol):
 
 
 def time_steps(ch, steps, warmup, label):
+    """Time `steps` whole LES steps after `warmup`; also sums the in-step
+    relaxation statistics (sweeps, kernel launches and their device time,
+    measured by the library with events on its stream)."""
     import torch
     for i in range(warmup):
         st = ch.step(1)
         print(f"[{label}] warmup step {i + 1}/{warmup}: sweeps {st['poisson']['sweeps']} "
               f"relres0 {st['poisson']['relres0']:.2e} cfl {st['cfl']:.3f}", flush=True)
     torch.cuda.synchronize()
-    sweeps = 0
+    acc = {"sweeps": 0, "launches": 0, "ms_relax": 0.0}
     t0 = time.perf_counter()
     for i in range(steps):
         st = ch.step(1)
-        sweeps += st["poisson"]["sweeps"]
+        for k in acc:
+            acc[k] += st["poisson"][k]
         print(f"[{label}] step {i + 1}/{steps}: sweeps {st['poisson']['sweeps']} outer {st['poisson']['outer']} "
               f"relres0 {st['poisson']['relres0']:.2e} relres {st['poisson']['relres']:.2e} "
-              f"ms {st['ms_total']:.1f} (poisson {st['ms_poisson']:.1f}) max_div {st['max_div']:.1e}", flush=True)
+              f"ms {st['ms_total']:.1f} (poisson {st['ms_poisson']:.1f}, sweeps {st['poisson']['ms_relax']:.1f}) "
+              f"max_div {st['max_div']:.1e}", flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dt, sweeps, st
+    return dt, acc, st
 
 
-def kernel_roofline(wl, nsweeps):
-    """Average duration of the FP32 relaxation sweep at this grid, timed with
-    events on the stream the library launches on (torch's current stream)."""
+def roofline_from_steps(n, acc, word_bytes, kernel):
+    """Roofline of the dominant kernel from the timed steps: one launch moves
+    3 words per cell of compulsory traffic (read p, read b, write p), so
+    achieved = 3 w n launches / device time of the sweep sequences."""
+    sec = acc["ms_relax"] * 1e-3
+    achieved = 3.0 * word_bytes * n * acc["launches"] / sec / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+            "launches": acc["launches"], "sweeps": acc["sweeps"],
+            "us_per_launch": round(1e6 * sec / acc["launches"], 2),
+            "effective_GBs": round(3.0 * word_bytes * n * acc["sweeps"] / sec / 1e9, 1),
+            "gcell_updates_per_s": round(n * acc["sweeps"] / sec / 1e9, 1)}
+
+
+def measured_traffic(nx, ny, nz, tblock):
+    """HBM bytes per launch of the relaxation kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
+    counters on a plain copy of known size); None if the summary is for
+    another kernel source, grid or fusion depth."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "relax_traffic.json")
+    src = os.path.join(ROOT, "paper_1511_07800_amd", "csrc", "stp_relax.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha or rec.get("grid") != [nx, ny, nz] or rec.get("sweeps_per_launch") != tblock:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def profile_kernels(wl):
+    """Kernels for counter collection: a torch copy of 64 Mi floats (512 MiB
+    moved: 256 MiB read, 256 MiB written), then 8 launches each of the fused
+    FP32 relaxation kernel and the single-sweep FP32 kernel."""
     import torch
     from paper_1511_07800_amd import Channel, inputs
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(4):
+        c.copy_(a)
+    torch.cuda.synchronize()
     nx, ny, nz = wl["nx"], wl["ny"], wl["nz"]
-    ch = Channel(nx, ny, nz, wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"], dt=wl["dt"])
     b = torch.from_numpy(inputs.poisson_rhs(nx, ny, nz, seed=1511)).float().cuda()
-    p = torch.zeros_like(b)
-    om = ch.schedule()
-    ws = [om[k % len(om)] for k in range(nsweeps)]
-    ch.relax(b, p, ws[:10])
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    ch.relax(b, p, ws)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / nsweeps
-    n = nx * ny * nz
-    bytes_per_sweep = 12.0 * n  # read p, read b, write p: 3 FP32 words per cell
-    achieved = bytes_per_sweep / (ms * 1e-3) / 1e9
-    ch.close()
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_relax<float>", "us_per_launch": round(ms * 1e3, 2),
-            "gcell_updates_per_s": round(n / (ms * 1e-3) / 1e9, 1)}
+    for tb in (4, 1):
+        ch = Channel(nx, ny, nz, wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"], dt=wl["dt"], tblock=tb)
+        p = torch.zeros_like(b)
+        om = ch.schedule()
+        ch.relax(b, p, [om[k % len(om)] for k in range(8 * tb)])
+        torch.cuda.synchronize()
+        ch.close()
+    print("profile-kernels done", flush=True)
 
 
-def cpu_baseline(wl):
+def cpu_baseline(wl, seconds=12.0):
     """The FP64 oracle's relaxation sweep on the host cores, on a bounded
-    sample: 8 sweeps of the same grid."""
+    sample: consecutive sweeps of the same grid (the schedule's weights in
+    order) for about `seconds` of wall time."""
     import numpy as np
     import oracle
     from paper_1511_07800_amd import inputs
@@ -114,15 +146,17 @@ def cpu_baseline(wl):
     b = inputs.poisson_rhs(nx, ny, nz, seed=1511)
     p = np.zeros_like(b)
     om = oracle.srj_schedule(nx, ny, nz, wl["lx"], wl["ly"], wl["lz"])
-    oracle.srj_sweep(P, om[0], p, b)
-    nsw = 8
+    p = oracle.srj_sweep(P, om[0], p, b)
+    nsw = 0
     t0 = time.perf_counter()
-    for k in range(nsw):
-        p = oracle.srj_sweep(P, om[k % len(om)], p, b)
+    while time.perf_counter() - t0 < seconds and nsw < 10000:
+        p = oracle.srj_sweep(P, om[nsw % len(om)], p, b)
+        nsw += 1
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(nsw * nx * ny * nz / dt / 1e9, 4), "unit": "Gcell-updates/s", "cores": cores,
-            "kind": "oracle", "sample": f"{nsw} FP64 SRJ sweeps of the {nx}x{ny}x{nz} grid ({dt:.1f} s)"}
+            "kind": "oracle", "sample": f"{nsw} consecutive FP64 SRJ sweeps of the {nx}x{ny}x{nz} grid "
+                                        f"({dt:.1f} s, OpenMP over z-planes)"}
 
 
 def main():
@@ -136,9 +170,12 @@ def main():
     torch.cuda.set_device(0)
     wl = workloads.params(args.workload)
     n = wl["nx"] * wl["ny"] * wl["nz"]
+    if args.profile_kernels:
+        profile_kernels(wl)
+        return
 
     ch = make_channel(wl, STP_MIXED, args.rtol)
-    t_mixed, sweeps_mixed, st_mixed = time_steps(ch, args.steps, args.warmup, "mixed")
+    t_mixed, acc_mixed, st_mixed = time_steps(ch, args.steps, args.warmup, "mixed")
     ch.close()
     del ch
     torch.cuda.empty_cache()
@@ -146,18 +183,20 @@ def main():
     fp64 = None
     if not args.no_fp64:
         ch = make_channel(wl, STP_FP64, args.rtol)
-        t64, sweeps64, _ = time_steps(ch, args.steps, args.warmup, "fp64")
+        t64, acc64, _ = time_steps(ch, args.steps, args.warmup, "fp64")
         fp64 = {"steps_per_s": round(args.steps / t64, 4), "ms_per_step": round(1e3 * t64 / args.steps, 2),
-                "sweeps_per_step": sweeps64 / args.steps,
-                "gcell_updates_per_s": round(sweeps64 * n / t64 / 1e9, 2)}
+                "sweeps_per_step": acc64["sweeps"] / args.steps,
+                "gcell_updates_per_s": round(acc64["sweeps"] * n / t64 / 1e9, 2),
+                "relax_kernel": roofline_from_steps(n, acc64, 8, "k_relax_fused<double,4,8>")}
         ch.close()
         del ch
         torch.cuda.empty_cache()
 
-    roof = kernel_roofline(wl, args.sweeps)
+    roof = roofline_from_steps(n, acc_mixed, 4, "k_relax_fused<float,4,8>")
+    roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
     cpu = None if args.no_cpu else cpu_baseline(wl)
 
-    value = sweeps_mixed * n / t_mixed / 1e9
+    value = acc_mixed["sweeps"] * n / t_mixed / 1e9
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Gcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t_mixed / args.steps, 2),
@@ -167,7 +206,8 @@ def main():
                    "poisson_rtol": args.rtol, "dt": wl["dt"], "les": wl["les"], "init": "laminar+10% noise"},
         "les_steps_per_s": {"mixed": round(args.steps / t_mixed, 4), "fp64": fp64["steps_per_s"] if fp64 else None,
                             "learned_mixed": None},
-        "sweeps_per_step": {"mixed": sweeps_mixed / args.steps, "fp64": fp64["sweeps_per_step"] if fp64 else None},
+        "sweeps_per_step": {"mixed": acc_mixed["sweeps"] / args.steps,
+                            "fp64": fp64["sweeps_per_step"] if fp64 else None},
         "fp64": fp64,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -104,7 +104,9 @@ typedef struct {
     const double* srj_omega;   /* host array of srj_m weights in sweep order (copied at init) */
     double srj_reduction;      /* built-in schedule: bound on one cycle's error reduction (e.g. 1e-3) */
     int32_t mixed_inner;       /* mixed mode: FP32 cycles per defect-correction pass (>= 1) */
-    int32_t tblock;            /* sweeps fused per relaxation launch: 1, 2 or 4 (0 selects 1) */
+    int32_t tblock;            /* sweeps fused per relaxation launch: 1, 2 or 4 (0 selects 4); grids with
+                                  nx < 64 or ny < 32 always run single sweeps.  Results are bitwise
+                                  identical for every value. */
     double cn_tol;             /* Crank-Nicolson iteration error target relative to the start (e.g. 1e-13) */
     void* stream;              /* hipStream_t for all work */
 } stp_config;
@@ -117,6 +119,9 @@ typedef struct {
     double relres0;    /* ||b - L p0||_2 / ||b||_2 before the solve */
     double relres;     /* after the solve */
     double bnorm;      /* ||b||_2 */
+    int32_t launches;  /* relaxation kernel launches (each runs tblock sweeps or fewer) */
+    int32_t pad;
+    double ms_relax;   /* device time of the back-to-back sweep sequences (events around each), ms */
 } stp_solve_stats;
 
 typedef struct {

@@ -35,10 +35,11 @@ class Config(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int32), ("outer", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("relres0", ctypes.c_double), ("relres", ctypes.c_double),
-                ("bnorm", ctypes.c_double)]
+                ("bnorm", ctypes.c_double), ("launches", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("ms_relax", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
 class StepStats(ctypes.Structure):
@@ -107,7 +108,7 @@ class Channel:
 
     def __init__(self, nx, ny, nz, lx, ly, lz, nu, dpdx, dt, les=0, cs=0.1, vd_a=25.0,
                  precision=STP_FP64, warm_start=STP_WS_PREV, poisson_rtol=1e-10, poisson_maxit=1000,
-                 omega=None, srj_reduction=1e-3, mixed_inner=1, tblock=1, cn_tol=1e-13, device=None):
+                 omega=None, srj_reduction=1e-3, mixed_inner=1, tblock=4, cn_tol=1e-13, device=None):
         import torch
         self.torch = torch
         self.lib = load_library()

@@ -32,7 +32,7 @@ struct stp_ctx {
     std::vector<double> omega;  // the relaxation cycle (weights)
     double D = 0.0;             // Jacobi diagonal 2/dx^2 + 2/dy^2 + 2/dz^2
     int step = 0;
-    hipEvent_t ev[4] = {};
+    hipEvent_t ev[6] = {};  // step start, solve start/end, step end; sweep sequence start/end
     std::string err;
 };
 
@@ -50,7 +50,7 @@ stp_config effective(const stp_config& c)
     stp_config e = c;
     if (e.srj_reduction == 0.0) e.srj_reduction = 1e-3;
     if (e.mixed_inner == 0) e.mixed_inner = 1;
-    if (e.tblock == 0) e.tblock = 1;
+    if (e.tblock == 0) e.tblock = 4;
     if (e.cn_tol == 0.0) e.cn_tol = 1e-13;
     return e;
 }
@@ -59,6 +59,7 @@ const char* validate(const stp_config& c)
 {
     if (c.nx < 1 || c.ny < 1 || c.nz < 2) return "grid: need nx >= 1, ny >= 1, nz >= 2";
     if ((long long)c.nx * c.ny * (c.nz + 1) > (1LL << 40)) return "grid too large";
+    if ((long long)c.nx * c.ny >= (1LL << 31)) return "grid plane too large (nx*ny >= 2^31)";
     if (!finite_pos(c.lx) || !finite_pos(c.ly) || !finite_pos(c.lz)) return "domain lengths must be finite and > 0";
     if (!finite_pos(c.nu)) return "nu must be finite and > 0";
     if (!finite_pos(c.dt)) return "dt must be finite and > 0";
@@ -78,7 +79,7 @@ const char* validate(const stp_config& c)
         return "srj_reduction must lie in (0, 1)";
     }
     if (c.mixed_inner < 1) return "mixed_inner must be >= 1";
-    if (c.tblock != 1) return "tblock must be 1";
+    if (c.tblock != 1 && c.tblock != 2 && c.tblock != 4) return "tblock must be 1, 2 or 4";
     if (!(c.cn_tol > 0.0 && c.cn_tol < 1.0)) return "cn_tol must lie in (0, 1)";
     return nullptr;
 }
@@ -206,27 +207,43 @@ stp_status readback(stp_ctx* ctx)
 // ping-ponging between *cur and *other; on return *cur holds the iterate.
 template <typename T>
 stp_status run_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, const double* omega, int m, long long first,
-                      long long count)
+                      long long count, int* launches = nullptr)
 {
-    const int tb = ctx->cfg.tblock;
+    // NT sweeps per launch where the grid allows it; a remainder of 2 or 3
+    // sweeps uses one fused pair, the rest single sweeps.
+    const int tb = relax_fusable(ctx->g) ? ctx->cfg.tblock : 1;
     long long s = 0;
     while (s < count) {
-        const int nf = (int)std::min<long long>(tb, count - s);
+        const long long left = count - s;
+        const int nf = left >= tb ? tb : (left >= 2 && tb >= 2 ? 2 : 1);
         Weights wts{};
         for (int f = 0; f < nf; ++f) wts.c[f] = omega[(first + s + f) % m] / ctx->D;
-        if (nf == 1 || tb == 1) {
-            for (int f = 0; f < nf; ++f) {
-                Weights one{};
-                one.c[0] = wts.c[f];
-                CHK(relax<T>(ctx->g, b, *cur, *other, one, 1, ctx->s));
-                std::swap(*cur, *other);
-            }
-        } else {
-            CHK(relax<T>(ctx->g, b, *cur, *other, wts, nf, ctx->s));
-            std::swap(*cur, *other);
-        }
+        CHK(relax<T>(ctx->g, b, *cur, *other, wts, nf, ctx->s));
+        std::swap(*cur, *other);
         s += nf;
+        if (launches) ++*launches;
     }
+    return STP_OK;
+}
+
+// run_sweeps between two events; adds the device time to st->ms_relax after
+// the next synchronisation (timed_flush).
+template <typename T>
+stp_status timed_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, long long count, stp_solve_stats* st)
+{
+    CHK(hipEventRecord(ctx->ev[4], ctx->s));
+    stp_status rc = run_sweeps<T>(ctx, b, cur, other, ctx->omega.data(), (int)ctx->omega.size(), 0, count,
+                                  &st->launches);
+    if (rc != STP_OK) return rc;
+    CHK(hipEventRecord(ctx->ev[5], ctx->s));
+    return STP_OK;
+}
+
+stp_status timed_flush(stp_ctx* ctx, stp_solve_stats* st)
+{
+    float ms = 0.f;
+    CHK(hipEventElapsedTime(&ms, ctx->ev[4], ctx->ev[5]));
+    st->ms_relax += ms;
     return STP_OK;
 }
 
@@ -252,19 +269,20 @@ stp_status solve_fp64(stp_ctx* ctx, const double* b, double* p, double* ptmp, do
         while (!(rn <= rtol * fb)) {
             if (!std::isfinite(rn)) { st->status = STP_ENAN; break; }
             if (cycles >= maxit) { st->status = STP_ENOCONV; break; }
-            if ((rc = run_sweeps<double>(ctx, b, &cur, &oth, ctx->omega.data(), m, 0, m)) != STP_OK) return rc;
+            if ((rc = timed_sweeps<double>(ctx, b, &cur, &oth, m, st)) != STP_OK) return rc;
             ++cycles;
             CHK(residual(ctx->g, b, cur, nullptr, ctx->part, ctx->res, ctx->s));
             if ((rc = readback(ctx)) != STP_OK) return rc;
+            if ((rc = timed_flush(ctx, st)) != STP_OK) return rc;
             rn = std::sqrt(ctx->host[RES_R2]);
             ++checks;
         }
     } else {
-        if ((rc = run_sweeps<double>(ctx, b, &cur, &oth, ctx->omega.data(), m, 0, (long long)m * maxit)) != STP_OK)
-            return rc;
+        if ((rc = timed_sweeps<double>(ctx, b, &cur, &oth, (long long)m * maxit, st)) != STP_OK) return rc;
         cycles = maxit;
         CHK(residual(ctx->g, b, cur, nullptr, ctx->part, ctx->res, ctx->s));
         if ((rc = readback(ctx)) != STP_OK) return rc;
+        if ((rc = timed_flush(ctx, st)) != STP_OK) return rc;
         rn = std::sqrt(ctx->host[RES_R2]);
         checks = 1;
         if (!std::isfinite(rn)) st->status = STP_ENAN;
@@ -299,11 +317,13 @@ stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, in
         float* cur = ctx->e0;
         float* oth = ctx->e1;
         CHK(fill(cur, 0.0f, ctx->g.n, ctx->s));
-        stp_status r2 = run_sweeps<float>(ctx, ctx->r32, &cur, &oth, ctx->omega.data(), m, 0, (long long)m * inner);
+        stp_status r2 = timed_sweeps<float>(ctx, ctx->r32, &cur, &oth, (long long)m * inner, st);
         if (r2 != STP_OK) return r2;
         CHK(add_correction(p, cur, ctx->g.n, ctx->s));
         CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s));
         r2 = readback(ctx);
+        if (r2 != STP_OK) return r2;
+        r2 = timed_flush(ctx, st);
         if (r2 != STP_OK) return r2;
         rn = std::sqrt(ctx->host[RES_R2]);
         ++outer;
@@ -504,7 +524,7 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
         delete ctx;
         return STP_ENOMEM;
     }
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 6; ++q)
         if (hipEventCreate(&ctx->ev[q]) != hipSuccess) {
             stp_destroy(ctx);
             return STP_EDEVICE;
@@ -655,7 +675,7 @@ stp_status stp_schedule(const stp_ctx* ctx, double* omega, int32_t cap, int32_t*
 stp_status stp_destroy(stp_ctx* ctx)
 {
     if (!ctx) return STP_OK;
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 6; ++q)
         if (ctx->ev[q]) (void)hipEventDestroy(ctx->ev[q]);
     if (ctx->host) (void)hipHostFree(ctx->host);
     delete ctx;

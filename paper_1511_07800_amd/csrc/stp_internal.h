@@ -79,6 +79,8 @@ hipError_t remove_mean(double* a, long long n, const double* res_sum, int res_ou
                        hipStream_t s);  // a -= res_sum[0]/n; optional sum of squares into res[res_out_sq]
 hipError_t sum_into(const double* a, long long n, double* part, double* res, int slot, hipStream_t s);
 
+// nfused = 1 (any grid) or 2, 4 (grids with nx >= 64 and ny >= 32).
+bool relax_fusable(const Geo& g);
 template <typename T>
 hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, int nfused, hipStream_t s);
 

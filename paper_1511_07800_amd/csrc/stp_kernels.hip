@@ -466,38 +466,6 @@ __global__ __launch_bounds__(256) void k_div(Geo g, int kchunk, const double* __
     if (threadIdx.x == 0 && threadIdx.y == 0) part[block_id()] = r;
 }
 
-// ---- Scheduled Relaxation Jacobi sweep (Sec. 3.4) ---------------------------
-
-// out = p + c (L_p p - b), c = omega/D.  L_p: 7-point Laplacian, periodic in
-// x and y, zero normal gradient at the walls (the missing neighbour equals the
-// centre value).  One thread per (i, j) column, z-march with the vertical
-// neighbours in registers.
-template <typename T>
-__global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchunk, const T* __restrict__ b,
-                                               const T* __restrict__ p, T* __restrict__ out, T c, T idx2, T idy2,
-                                               T idz2)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= nx || j >= ny) return;
-    const long long plane = (long long)nx * ny;
-    const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
-    const int jm = j == 0 ? ny - 1 : j - 1, jp = j == ny - 1 ? 0 : j + 1;
-    const long long row = (long long)nx * j, rowm = (long long)nx * jm, rowp = (long long)nx * jp;
-    const int k0 = blockIdx.z * kchunk, k1 = min(nz, k0 + kchunk);
-    long long o = plane * k0;
-    T pc = p[o + row + i];
-    T pb = k0 > 0 ? p[o - plane + row + i] : pc;
-    for (int k = k0; k < k1; ++k, o += plane) {
-        const T pt = k + 1 < nz ? p[o + plane + row + i] : pc;
-        const T lap = (p[o + row + im] + p[o + row + ip] - T(2) * pc) * idx2 +
-                      (p[o + rowm + i] + p[o + rowp + i] - T(2) * pc) * idy2 + ((pt - pc) + (pb - pc)) * idz2;
-        out[o + row + i] = pc + c * (lap - b[o + row + i]);
-        pb = pc;
-        pc = pt;
-    }
-}
-
 // r = b - L_p p in FP64 with partial sums of r^2; optional FP32 copy of r.
 __global__ __launch_bounds__(256) void k_residual(Geo g, int kchunk, const double* __restrict__ b,
                                                   const double* __restrict__ p, float* __restrict__ r32,
@@ -714,18 +682,6 @@ hipError_t sum_into(const double* a, long long n, double* part, double* res, int
     if (e != hipSuccess) return e;
     return finalize(part, nb, 1, 0u, res, slot, s);
 }
-
-template <typename T>
-hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, int nfused, hipStream_t s)
-{
-    if (nfused != 1) return hipErrorInvalidValue;
-    const March m = march_shape(g, 2048);
-    hipLaunchKernelGGL(k_relax<T>, m.grid, m.block, 0, s, g.nx, g.ny, g.nz, m.kchunk, b, p, out, (T)wts.c[0],
-                       (T)g.idx2, (T)g.idy2, (T)g.idz2);
-    return hipGetLastError();
-}
-template hipError_t relax<double>(const Geo&, const double*, const double*, double*, const Weights&, int, hipStream_t);
-template hipError_t relax<float>(const Geo&, const float*, const float*, float*, const Weights&, int, hipStream_t);
 
 hipError_t residual(const Geo& g, const double* b, const double* p, float* r32, double* part, double* res,
                     hipStream_t s)

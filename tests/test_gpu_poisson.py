@@ -205,3 +205,42 @@ def test_full_size_sweep_sampled(gpu, dtype):
     ref = oracle.srj_sweep_at(P, omega, p, b, cells)
     tol = 1e-14 if dtype == "f64" else 2e-6
     assert rel_max(got[cells], ref) <= tol * omega
+
+
+@pytest.mark.parametrize("g", [(70, 45, 33, 2.0, 1.5, 1.0), (130, 64, 40, 4.0, 2.0, 2.0), (64, 32, 5, 1.0, 1.0, 1.0)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nt", [2, 4])
+def test_fused_sweeps_equal_single_sweeps_bitwise(gpu, g, dtype, nt):
+    """NT sweeps fused into one launch (LDS tile, z-march) reproduce NT single
+    sweeps bit for bit, including ragged tiles, the periodic seams and the walls."""
+    import torch
+    print(f"fused grid={g} dtype={dtype} nt={nt}", flush=True)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    r = inputs.rng(19)
+    p = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
+    b = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
+    om = [1.3, 57.0, 0.6, 3.1, 11.0, 0.9, 2.2, 40.0][: 2 * nt]
+    ch1 = channel(g, tblock=1)
+    chf = channel(g, tblock=nt)
+    p1 = p.clone()
+    pf = p.clone()
+    ch1.relax(b, p1, om)
+    chf.relax(b, pf, om)
+    torch.cuda.synchronize()
+    assert torch.equal(p1, pf)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_with_fused_sweeps_bitwise(gpu, precision):
+    import torch
+    g = (96, 40, 24, 4.0, 2.0, 2.0)
+    b = to_dev(torch, inputs.poisson_rhs(g[0], g[1], g[2], seed=20))
+    out = []
+    for tb in (1, 4):
+        ch = channel(g, tblock=tb, precision=precision)
+        pd = torch.zeros_like(b)
+        stats, rc = ch.poisson_solve(b, pd, 1e-10, 100)
+        assert rc == 0
+        out.append((stats["cycles"], pd.cpu()))
+    assert out[0][0] == out[1][0]
+    assert torch.equal(out[0][1], out[1][1])
