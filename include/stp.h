@@ -77,8 +77,10 @@ typedef enum {
 } stp_precision;
 
 typedef enum {
-    STP_WS_PREV = 0,  /* Poisson solve starts from p^n */
-    STP_WS_ZERO = 1   /* Poisson solve starts from 0 */
+    STP_WS_PREV = 0,    /* Poisson solve starts from p^n */
+    STP_WS_ZERO = 1,    /* Poisson solve starts from 0 */
+    STP_WS_LEARNED = 2  /* from the network's guess (stp_net_init first), or from p^n when that
+                           has the smaller residual */
 } stp_warm;
 
 typedef enum {
@@ -136,6 +138,11 @@ typedef struct {
     double nut_max;    /* max nu_T */
     double ms_total;   /* wall time of the step (stream-ordered events), ms */
     double ms_poisson; /* of which the Poisson solve, ms */
+    double relres_prev;    /* learned warm start: relative residual of p^n ... */
+    double relres_learned; /* ... and of the network's guess (0 when not used) */
+    int32_t learned_used;  /* 1 if the solve started from the network's guess */
+    int32_t pad;
+    double ms_net;         /* network inference time, ms */
 } stp_step_stats;
 
 /* Bytes of device workspace the configuration needs (0 if cfg is invalid). */
@@ -181,6 +188,50 @@ stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape
 
 /* The relaxation cycle in use: writes min(cap, M) weights, *m = M. */
 stp_status stp_schedule(const stp_ctx* ctx, double* omega, int32_t cap, int32_t* m);
+
+/* ---- learned warm start ------------------------------------------------------
+ * Not part of the paper: a 3-level 3-D convolutional network (16/32/64
+ * channels, 3x3x3 kernels, ReLU, 2x average pooling, nearest upsampling with
+ * skip concatenation; periodic in x and y, zero padding beyond the walls)
+ * predicts the pressure increment of a step from (b, p^n).  BF16 weights and
+ * activations, FP32 accumulation on the matrix cores.  Inputs are scaled by
+ * s = rms(p^n - mean p^n) (rms(b/D) if that is 0): x = (b/(D s), (p^n - mean)/s);
+ * the guess is p^n + s y.  The relaxation always runs to the same residual,
+ * so the network only changes the starting point.  Requires nx, ny, nz
+ * divisible by 4.  Parameters: one FP32 vector, per layer W[27][cout][cin]
+ * (tap = 9(dz+1) + 3(dy+1) + (dx+1)) then bias[cout], channel counts padded
+ * to multiples of 16 with zero weights (layout from stp_net_layout). */
+
+/* Bytes of device workspace the network needs for this context's grid
+ * (training adds the backward buffers); 0 if the grid is not supported. */
+size_t stp_net_workspace_bytes(const stp_ctx* ctx, int32_t training);
+
+/* Carve the network out of a caller-owned device workspace (kept alive until
+ * stp_destroy), initialise the weights from seed (He-uniform), zero the
+ * biases.  training = 0 allows prediction only. */
+stp_status stp_net_init(stp_ctx* ctx, void* dev_workspace, size_t bytes, int32_t training, uint64_t seed);
+
+/* Borrowed device pointers to the FP32 parameter vector and its gradient
+ * (gradient NULL without training) and their length. */
+stp_status stp_net_params(stp_ctx* ctx, float** params, float** grads, int64_t* count);
+
+/* Layer l (0..5): out = {weight offset, bias offset, cin, cout, logical cin, logical cout}. */
+stp_status stp_net_layout(const stp_ctx* ctx, int32_t layer, int64_t out[6]);
+
+/* After the caller wrote the parameter vector: refresh the BF16 copies and
+ * restart Adam. */
+stp_status stp_net_sync(stp_ctx* ctx);
+
+/* p_guess = p_prev + s y(b, p_prev); FP64 device arrays of nx*ny*nz (borrowed). */
+stp_status stp_net_predict(stp_ctx* ctx, const void* b_dev, const void* p_prev_dev, void* p_guess_dev);
+
+/* One training step on a (b, p_prev, p_next) triple from the solver: forward,
+ * loss = mean((y - (p_next - p_prev)/s)^2), backward into the gradient
+ * vector, then Adam (beta 0.9, 0.999, eps 1e-8) with learning rate lr when
+ * lr > 0 (lr = 0 leaves the weights and only computes gradients).  *loss
+ * (nullable) receives the loss; synchronises when loss is not NULL. */
+stp_status stp_net_train_step(stp_ctx* ctx, const void* b_dev, const void* p_prev_dev, const void* p_next_dev,
+                              float lr, double* loss);
 
 /* Release the context (not the caller's workspace). NULL is accepted. */
 stp_status stp_destroy(stp_ctx* ctx);

@@ -7,7 +7,7 @@ _LIB_PATH = os.path.join(HERE, "libstp.so")
 
 STP_OK, STP_EINVAL, STP_ENOMEM, STP_EDEVICE, STP_ENOCONV, STP_ENAN = 0, -1, -2, -3, -4, -5
 STP_FP64, STP_MIXED = 0, 1
-STP_WS_PREV, STP_WS_ZERO = 0, 1
+STP_WS_PREV, STP_WS_ZERO, STP_WS_LEARNED = 0, 1, 2
 STP_U, STP_V, STP_W, STP_P, STP_NUT, STP_RHS = range(6)
 STP_DTYPE_F64, STP_DTYPE_F32 = 0, 1
 
@@ -46,10 +46,12 @@ class StepStats(ctypes.Structure):
     _fields_ = [("poisson", SolveStats), ("step", ctypes.c_int32), ("cn_sweeps", ctypes.c_int32),
                 ("max_div", ctypes.c_double), ("u_bulk", ctypes.c_double), ("u_max", ctypes.c_double),
                 ("cfl", ctypes.c_double), ("u_centre", ctypes.c_double), ("nut_max", ctypes.c_double),
-                ("ms_total", ctypes.c_double), ("ms_poisson", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("ms_poisson", ctypes.c_double),
+                ("relres_prev", ctypes.c_double), ("relres_learned", ctypes.c_double),
+                ("learned_used", ctypes.c_int32), ("pad", ctypes.c_int32), ("ms_net", ctypes.c_double)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "poisson"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("poisson", "pad")}
         d["poisson"] = self.poisson.as_dict()
         return d
 
@@ -87,6 +89,20 @@ def load_library():
     L.stp_fields.restype = i32
     L.stp_schedule.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
     L.stp_schedule.restype = i32
+    L.stp_net_workspace_bytes.argtypes = [vp, i32]
+    L.stp_net_workspace_bytes.restype = ctypes.c_size_t
+    L.stp_net_init.argtypes = [vp, vp, ctypes.c_size_t, i32, ctypes.c_uint64]
+    L.stp_net_init.restype = i32
+    L.stp_net_params.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64)]
+    L.stp_net_params.restype = i32
+    L.stp_net_layout.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
+    L.stp_net_layout.restype = i32
+    L.stp_net_sync.argtypes = [vp]
+    L.stp_net_sync.restype = i32
+    L.stp_net_predict.argtypes = [vp, vp, vp, vp]
+    L.stp_net_predict.restype = i32
+    L.stp_net_train_step.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.POINTER(dbl)]
+    L.stp_net_train_step.restype = i32
     L.stp_destroy.argtypes = [vp]
     L.stp_destroy.restype = i32
     L.stp_last_error.argtypes = [vp]
@@ -198,6 +214,55 @@ class Channel:
         self._check(self.lib.stp_residual_norm(self.handle, _dptr(b), _dptr(p), ctypes.byref(out)),
                     "stp_residual_norm")
         return out.value
+
+    # -- learned warm start ---------------------------------------------------
+    def net_init(self, training=True, seed=0):
+        t = self.torch
+        nbytes = self.lib.stp_net_workspace_bytes(self.handle, 1 if training else 0)
+        if nbytes == 0:
+            raise StpError(STP_EINVAL, "network needs nx, ny, nz divisible by 4")
+        self.net_workspace = t.empty(nbytes + 256, dtype=t.uint8, device=self.device)
+        base = self.net_workspace.data_ptr()
+        off = (-base) % 256
+        self._check(self.lib.stp_net_init(self.handle, ctypes.c_void_p(base + off), nbytes, 1 if training else 0,
+                                          int(seed)), "stp_net_init")
+
+    def net_params(self):
+        """(params, grads) as borrowed float32 torch views (grads None without training)."""
+        t = self.torch
+        p = ctypes.c_void_p()
+        g = ctypes.c_void_p()
+        n = ctypes.c_int64()
+        self._check(self.lib.stp_net_params(self.handle, ctypes.byref(p), ctypes.byref(g), ctypes.byref(n)),
+                    "stp_net_params")
+        base = self.net_workspace.data_ptr()
+        def view(ptr):
+            if not ptr.value:
+                return None
+            off = ptr.value - base
+            return self.net_workspace[off:off + 4 * n.value].view(t.float32)
+        return view(p), view(g)
+
+    def net_layout(self):
+        out = []
+        for l in range(6):
+            arr = (ctypes.c_int64 * 6)()
+            self._check(self.lib.stp_net_layout(self.handle, l, arr), "stp_net_layout")
+            out.append(dict(w_off=arr[0], b_off=arr[1], cin=arr[2], cout=arr[3], cin_logical=arr[4],
+                            cout_logical=arr[5]))
+        return out
+
+    def net_sync(self):
+        self._check(self.lib.stp_net_sync(self.handle), "stp_net_sync")
+
+    def net_predict(self, b, p_prev, p_guess):
+        self._check(self.lib.stp_net_predict(self.handle, _dptr(b), _dptr(p_prev), _dptr(p_guess)), "stp_net_predict")
+
+    def net_train_step(self, b, p_prev, p_next, lr):
+        loss = ctypes.c_double()
+        self._check(self.lib.stp_net_train_step(self.handle, _dptr(b), _dptr(p_prev), _dptr(p_next), float(lr),
+                                                ctypes.byref(loss)), "stp_net_train_step")
+        return loss.value
 
     def close(self):
         if getattr(self, "handle", None) is not None:

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstp.so")
-SOURCES = ["stp_kernels.hip", "stp_relax.hip", "stp_api.hip"]
+SOURCES = ["stp_kernels.hip", "stp_relax.hip", "stp_net.hip", "stp_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

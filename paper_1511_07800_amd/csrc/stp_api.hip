@@ -4,6 +4,7 @@
 // only orders launches on the caller's stream and reads back scalars.
 #include "stp.h"
 #include "stp_internal.h"
+#include "stp_net.h"
 
 #include <algorithm>
 #include <cmath>
@@ -32,6 +33,7 @@ struct stp_ctx {
     std::vector<double> omega;  // the relaxation cycle (weights)
     double D = 0.0;             // Jacobi diagonal 2/dx^2 + 2/dy^2 + 2/dz^2
     int step = 0;
+    stp::NetModel* net = nullptr;
     hipEvent_t ev[6] = {};  // step start, solve start/end, step end; sweep sequence start/end
     std::string err;
 };
@@ -67,7 +69,8 @@ const char* validate(const stp_config& c)
     if (c.les != 0 && c.les != 1) return "les must be 0 or 1";
     if (c.les && (!(c.cs >= 0.0) || !std::isfinite(c.cs) || !finite_pos(c.vd_a))) return "les: need cs >= 0, vd_a > 0";
     if (c.precision != STP_FP64 && c.precision != STP_MIXED) return "precision must be STP_FP64 or STP_MIXED";
-    if (c.warm_start != STP_WS_PREV && c.warm_start != STP_WS_ZERO) return "warm_start must be STP_WS_PREV or STP_WS_ZERO";
+    if (c.warm_start != STP_WS_PREV && c.warm_start != STP_WS_ZERO && c.warm_start != STP_WS_LEARNED)
+        return "warm_start must be STP_WS_PREV, STP_WS_ZERO or STP_WS_LEARNED";
     if (!(c.poisson_rtol >= 0.0) || !std::isfinite(c.poisson_rtol)) return "poisson_rtol must be >= 0";
     if (c.poisson_maxit < 1) return "poisson_maxit must be >= 1";
     if (c.srj_m < 0) return "srj_m must be >= 0";
@@ -429,6 +432,33 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
 
     // 5. SRJ pressure solve from the warm start (Sec. 3.4)
     if (c.warm_start == STP_WS_ZERO) CHK(fill(ctx->p, 0.0, g.n, s));
+    if (c.warm_start == STP_WS_LEARNED) {
+        if (!ctx->net) {
+            ctx->err = "STP_WS_LEARNED needs stp_net_init";
+            return STP_EINVAL;
+        }
+        // guess into ptmp; keep whichever of p^n and the guess has the smaller residual
+        CHK(hipEventRecord(ctx->ev[4], s));
+        CHK(ctx->net->predict(ctx->b, ctx->p, ctx->ptmp));
+        CHK(hipEventRecord(ctx->ev[5], s));
+        CHK(residual(g, ctx->b, ctx->p, nullptr, ctx->part, ctx->res, s));
+        if ((rc = readback(ctx)) != STP_OK) return rc;
+        const double r_prev = std::sqrt(ctx->host[RES_R2]);
+        CHK(residual(g, ctx->b, ctx->ptmp, nullptr, ctx->part, ctx->res, s));
+        if ((rc = readback(ctx)) != STP_OK) return rc;
+        const double r_net = std::sqrt(ctx->host[RES_R2]);
+        const double bn = std::sqrt(ctx->host[RES_B2]);
+        const double fb = bn > 1e-300 ? bn : 1e-300;
+        st.relres_prev = r_prev / fb;
+        st.relres_learned = r_net / fb;
+        if (std::isfinite(r_net) && r_net < r_prev) {
+            CHK(copy(ctx->p, ctx->ptmp, g.n, s));
+            st.learned_used = 1;
+        }
+        float msn = 0.f;
+        CHK(hipEventElapsedTime(&msn, ctx->ev[4], ctx->ev[5]));
+        st.ms_net = msn;
+    }
     CHK(hipEventRecord(ctx->ev[1], s));
     if ((rc = solve(ctx, ctx->b, ctx->p, c.poisson_rtol, c.poisson_maxit, &st.poisson)) != STP_OK) return rc;
     CHK(hipEventRecord(ctx->ev[2], s));
@@ -672,12 +702,106 @@ stp_status stp_schedule(const stp_ctx* ctx, double* omega, int32_t cap, int32_t*
     return STP_OK;
 }
 
+size_t stp_net_workspace_bytes(const stp_ctx* ctx, int32_t training)
+{
+    if (!ctx) return 0;
+    return stp::NetModel::workspace_bytes(ctx->g.nx, ctx->g.ny, ctx->g.nz, training != 0);
+}
+
+stp_status stp_net_init(stp_ctx* ctx, void* ws, size_t bytes, int32_t training, uint64_t seed)
+{
+    if (!ctx) return STP_EINVAL;
+    ctx->err.clear();
+    const size_t need = stp::NetModel::workspace_bytes(ctx->g.nx, ctx->g.ny, ctx->g.nz, training != 0);
+    if (need == 0) {
+        ctx->err = "stp_net_init: grid dimensions must be divisible by 4";
+        return STP_EINVAL;
+    }
+    if (!ws || bytes < need) {
+        ctx->err = "stp_net_init: workspace too small";
+        return STP_ENOMEM;
+    }
+    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
+        ctx->err = "stp_net_init: workspace must be 256-byte aligned";
+        return STP_EINVAL;
+    }
+    delete ctx->net;
+    ctx->net = new (std::nothrow) stp::NetModel(ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->D, training != 0, ws, ctx->s);
+    if (!ctx->net) return STP_ENOMEM;
+    CHK(ctx->net->init_params(seed));
+    CHK(hipStreamSynchronize(ctx->s));
+    return STP_OK;
+}
+
+stp_status stp_net_params(stp_ctx* ctx, float** params, float** grads, int64_t* count)
+{
+    if (!ctx || !ctx->net || !params || !count) return STP_EINVAL;
+    *params = ctx->net->params();
+    if (grads) *grads = ctx->net->grads();
+    *count = ctx->net->param_count();
+    return STP_OK;
+}
+
+stp_status stp_net_layout(const stp_ctx* ctx, int32_t layer, int64_t out[6])
+{
+    if (!ctx || !ctx->net || !out || layer < 0 || layer >= stp::NetModel::kLayers) return STP_EINVAL;
+    const stp::NetLayer& l = ctx->net->layer(layer);
+    out[0] = l.w_off;
+    out[1] = l.b_off;
+    out[2] = l.cin;
+    out[3] = l.cout;
+    out[4] = l.cin_logical;
+    out[5] = l.cout_logical;
+    return STP_OK;
+}
+
+stp_status stp_net_sync(stp_ctx* ctx)
+{
+    if (!ctx || !ctx->net) return STP_EINVAL;
+    ctx->err.clear();
+    CHK(ctx->net->sync());
+    return STP_OK;
+}
+
+stp_status stp_net_predict(stp_ctx* ctx, const void* b, const void* p_prev, void* p_guess)
+{
+    if (!ctx) return STP_EINVAL;
+    ctx->err.clear();
+    if (!ctx->net || !b || !p_prev || !p_guess) {
+        ctx->err = "stp_net_predict: network not initialised or NULL argument";
+        return STP_EINVAL;
+    }
+    CHK(ctx->net->predict(static_cast<const double*>(b), static_cast<const double*>(p_prev),
+                          static_cast<double*>(p_guess)));
+    return STP_OK;
+}
+
+stp_status stp_net_train_step(stp_ctx* ctx, const void* b, const void* p_prev, const void* p_next, float lr,
+                              double* loss)
+{
+    if (!ctx) return STP_EINVAL;
+    ctx->err.clear();
+    if (!ctx->net || !b || !p_prev || !p_next || !(lr >= 0.f) || !std::isfinite(lr)) {
+        ctx->err = "stp_net_train_step: network not initialised for training or bad argument";
+        return STP_EINVAL;
+    }
+    CHK(ctx->net->train_step(static_cast<const double*>(b), static_cast<const double*>(p_prev),
+                             static_cast<const double*>(p_next), lr, ctx->res + RES_NET_LOSS));
+    if (loss) {
+        stp_status rc = readback(ctx);
+        if (rc != STP_OK) return rc;
+        *loss = ctx->host[RES_NET_LOSS];
+    }
+    return STP_OK;
+}
+
 stp_status stp_destroy(stp_ctx* ctx)
 {
     if (!ctx) return STP_OK;
     for (int q = 0; q < 6; ++q)
         if (ctx->ev[q]) (void)hipEventDestroy(ctx->ev[q]);
     if (ctx->host) (void)hipHostFree(ctx->host);
+    delete ctx->net;
     delete ctx;
     return STP_OK;
 }

@@ -34,6 +34,7 @@ enum ResSlot {
     RES_R2 = 2,      // sum r^2 of the last residual
     RES_SUM_P = 3,   // sum p
     RES_NUT_MAX = 4,
+    RES_NET_LOSS = 5,
     RES_DIAG = 8,    // 5 values: max|div|, sum u, max|u|, max cfl, centreline sum
     RES_COUNT = 16
 };
