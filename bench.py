@@ -35,18 +35,19 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start run")
     ap.add_argument("--sweeps", type=int, default=200, help="sweeps in the kernel roofline timing")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run a plain copy of known size and the relaxation kernels (for rocprofv3 counters)")
     return ap.parse_args()
 
 
-def make_channel(wl, precision, rtol):
+def make_channel(wl, precision, rtol, warm_start=0):
     import torch
     from paper_1511_07800_amd import Channel, inputs
     ch = Channel(wl["nx"], wl["ny"], wl["nz"], wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"],
                  dt=wl["dt"], les=wl["les"], cs=wl.get("cs", 0.1), vd_a=wl.get("vd_a", 25.0), precision=precision,
-                 poisson_rtol=rtol, poisson_maxit=200)
+                 poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start)
     u, v, w = inputs.channel_state(wl["nx"], wl["ny"], wl["nz"], wl["lz"], wl["nu"], wl["dpdx"],
                                    noise=wl.get("noise", 0.0), seed=wl.get("seed", 0))
     for k, a in enumerate((u, v, w)):
@@ -74,7 +75,9 @@ def time_steps(ch, steps, warmup, label):
         print(f"[{label}] step {i + 1}/{steps}: sweeps {st['poisson']['sweeps']} outer {st['poisson']['outer']} "
               f"relres0 {st['poisson']['relres0']:.2e} relres {st['poisson']['relres']:.2e} "
               f"ms {st['ms_total']:.1f} (poisson {st['ms_poisson']:.1f}, sweeps {st['poisson']['ms_relax']:.1f}) "
-              f"max_div {st['max_div']:.1e}", flush=True)
+              f"max_div {st['max_div']:.1e}" + (f" net {st['ms_net']:.1f} ms relres p^n {st['relres_prev']:.2e} "
+                                                 f"guess {st['relres_learned']:.2e}" if st['ms_net'] > 0 else ""),
+              flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return dt, acc, st
@@ -192,6 +195,21 @@ def main():
         del ch
         torch.cuda.empty_cache()
 
+    learned = None
+    if not args.no_learned:
+        from paper_1511_07800_amd import STP_WS_LEARNED, warmstart
+        ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED)
+        ch.net_init(training=False)
+        warmstart.load_weights(ch)
+        tl, accl, stl = time_steps(ch, args.steps, args.warmup, "learned+mixed")
+        learned = {"steps_per_s": round(args.steps / tl, 4), "ms_per_step": round(1e3 * tl / args.steps, 2),
+                   "sweeps_per_step": accl["sweeps"] / args.steps, "ms_net_last": round(stl["ms_net"], 2),
+                   "relres_prev_last": stl["relres_prev"], "relres_learned_last": stl["relres_learned"],
+                   "weights": "paper_1511_07800_amd/weights/warmstart_les.npy (trained on 256x128x128 triples)"}
+        ch.close()
+        del ch
+        torch.cuda.empty_cache()
+
     roof = roofline_from_steps(n, acc_mixed, 4, "k_relax_fused<float,4,8>")
     roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
     cpu = None if args.no_cpu else cpu_baseline(wl)
@@ -205,10 +223,12 @@ def main():
         "config": {"workload": args.workload, "grid": [wl["nx"], wl["ny"], wl["nz"]], "precision": "mixed",
                    "poisson_rtol": args.rtol, "dt": wl["dt"], "les": wl["les"], "init": "laminar+10% noise"},
         "les_steps_per_s": {"mixed": round(args.steps / t_mixed, 4), "fp64": fp64["steps_per_s"] if fp64 else None,
-                            "learned_mixed": None},
+                            "learned_mixed": learned["steps_per_s"] if learned else None},
         "sweeps_per_step": {"mixed": acc_mixed["sweeps"] / args.steps,
-                            "fp64": fp64["sweeps_per_step"] if fp64 else None},
+                            "fp64": fp64["sweeps_per_step"] if fp64 else None,
+                            "learned_mixed": learned["sweeps_per_step"] if learned else None},
         "fp64": fp64,
+        "learned_mixed": learned,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

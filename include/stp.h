@@ -194,9 +194,11 @@ stp_status stp_schedule(const stp_ctx* ctx, double* omega, int32_t cap, int32_t*
  * channels, 3x3x3 kernels, ReLU, 2x average pooling, nearest upsampling with
  * skip concatenation; periodic in x and y, zero padding beyond the walls)
  * predicts the pressure increment of a step from (b, p^n).  BF16 weights and
- * activations, FP32 accumulation on the matrix cores.  Inputs are scaled by
- * s = rms(p^n - mean p^n) (rms(b/D) if that is 0): x = (b/(D s), (p^n - mean)/s);
- * the guess is p^n + s y.  The relaxation always runs to the same residual,
+ * activations, FP32 accumulation on the matrix cores.  The exact increment is
+ * L^-1 r with r = b - L p^n, so the inputs are the residual (computed in
+ * FP64) and p^n, each scaled by its own rms: x = (r/(D s_r), (p^n - mean)/s_p),
+ * s_r = rms(r/D), s_p = rms(p^n - mean p^n) (1 where zero); the guess is
+ * p^n + s_r y.  The relaxation always runs to the same residual,
  * so the network only changes the starting point.  Requires nx, ny, nz
  * divisible by 4.  Parameters: one FP32 vector, per layer W[27][cout][cin]
  * (tap = 9(dz+1) + 3(dy+1) + (dx+1)) then bias[cout], channel counts padded
@@ -226,7 +228,7 @@ stp_status stp_net_sync(stp_ctx* ctx);
 stp_status stp_net_predict(stp_ctx* ctx, const void* b_dev, const void* p_prev_dev, void* p_guess_dev);
 
 /* One training step on a (b, p_prev, p_next) triple from the solver: forward,
- * loss = mean((y - (p_next - p_prev)/s)^2), backward into the gradient
+ * loss = mean((y - (p_next - p_prev)/s_r)^2), backward into the gradient
  * vector, then Adam (beta 0.9, 0.999, eps 1e-8) with learning rate lr when
  * lr > 0 (lr = 0 leaves the weights and only computes gradients).  *loss
  * (nullable) receives the loss; synchronises when loss is not NULL. */

@@ -22,10 +22,12 @@ walls in z.  Architecture (3 levels, 16/32/64 channels):
     y  = conv6(d1)                            1 channel, linear
 pool: mean of 2x2x2 blocks; up: nearest-neighbour copy to 2x2x2 blocks.
 
-Normalisation (one scale per sample, from the inputs only):
-    s = rms(p_prev - mean(p_prev)), or rms(b / D) if that is 0,
-    x = [b / (D s), (p_prev - mean(p_prev)) / s],
-    prediction p_guess = p_prev + s y,  training target t = (p_next - p_prev) / s,
+Inputs and scaling (from b and p_prev only).  The exact increment is
+p_next - p_prev = L^-1 (b - L p_prev), a linear map of the residual
+r = b - L p_prev, so the network sees that residual, computed in FP64:
+    s_r = rms(r / D) (1 if that is 0),  s_p = rms(p_prev - mean(p_prev)) (1 if 0),
+    x = [r / (D s_r), (p_prev - mean(p_prev)) / s_p],
+    prediction p_guess = p_prev + s_r y,  training target t = (p_next - p_prev) / s_r,
     loss = mean over cells of (y - t)^2.
 """
 import numpy as np
@@ -111,17 +113,18 @@ def init_params(seed=0):
     return params
 
 
-def normalise(b, p_prev, D):
-    """Inputs (nz, ny, nx) float64 -> (x, s, mean(p_prev))."""
-    pm = p_prev.mean()
-    dp = p_prev - pm
-    s = np.sqrt(np.mean(dp * dp))
-    if s == 0.0:
-        s = np.sqrt(np.mean((b / D) ** 2))
-    if s == 0.0:
-        s = 1.0
-    x = np.stack([b / (D * s), dp / s], axis=-1)
-    return x, s, pm
+def normalise(b, p_prev, lap_p_prev, D):
+    """Inputs (nz, ny, nx) float64; lap_p_prev = L p_prev.  Returns (x, s_r)."""
+    rd = (b - lap_p_prev) / D
+    s_r = np.sqrt(np.mean(rd * rd))
+    if s_r == 0.0:
+        s_r = 1.0
+    dp = p_prev - p_prev.mean()
+    s_p = np.sqrt(np.mean(dp * dp))
+    if s_p == 0.0:
+        s_p = 1.0
+    x = np.stack([rd / s_r, dp / s_p], axis=-1)
+    return x, s_r
 
 
 def forward(params, x, round_bf16=False):
@@ -185,7 +188,7 @@ def adam_step(params, grads, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return out
 
 
-def predict(params, b, p_prev, D, round_bf16=False):
-    x, s, _ = normalise(b, p_prev, D)
+def predict(params, b, p_prev, lap_p_prev, D, round_bf16=False):
+    x, s_r = normalise(b, p_prev, lap_p_prev, D)
     y, _ = forward(params, x, round_bf16)
-    return p_prev + s * y
+    return p_prev + s_r * y

@@ -726,7 +726,8 @@ stp_status stp_net_init(stp_ctx* ctx, void* ws, size_t bytes, int32_t training, 
         return STP_EINVAL;
     }
     delete ctx->net;
-    ctx->net = new (std::nothrow) stp::NetModel(ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->D, training != 0, ws, ctx->s);
+    ctx->net = new (std::nothrow) stp::NetModel(ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->g.idx2, ctx->g.idy2, ctx->g.idz2,
+                                                training != 0, ws, ctx->s);
     if (!ctx->net) return STP_ENOMEM;
     CHK(ctx->net->init_params(seed));
     CHK(hipStreamSynchronize(ctx->s));

@@ -26,7 +26,9 @@ public:
     static size_t workspace_bytes(int nx, int ny, int nz, bool training);
     static bool grid_ok(int nx, int ny, int nz);
 
-    NetModel(int nx, int ny, int nz, double D, bool training, void* ws, hipStream_t s);
+    // idx2, idy2, idz2: 1/dx^2, 1/dy^2, 1/dz^2 of the grid (for the residual input)
+    NetModel(int nx, int ny, int nz, double idx2, double idy2, double idz2, bool training, void* ws,
+             hipStream_t s);
 
     long long param_count() const { return nparam_; }
     float* params() { return P_; }
@@ -35,9 +37,9 @@ public:
 
     hipError_t init_params(uint64_t seed);
     hipError_t sync();  // BF16 copies from the FP32 master weights; Adam state reset
-    // p_guess = p_prev + s y(b, p_prev); all FP64 device arrays of nx*ny*nz
+    // p_guess = p_prev + s_r y(b, p_prev); all FP64 device arrays of nx*ny*nz
     hipError_t predict(const double* b, const double* p_prev, double* p_guess);
-    // forward + MSE loss against (p_next - p_prev)/s + backward into grads();
+    // forward + MSE loss against (p_next - p_prev)/s_r + backward into grads();
     // Adam update with lr when lr > 0.  *loss_dev receives the loss (device).
     hipError_t train_step(const double* b, const double* p_prev, const double* p_next, float lr, double* loss_dev);
 
@@ -49,7 +51,7 @@ private:
 
     int nx_[3], ny_[3], nz_[3];
     long long nv_[3];
-    double D_;
+    double D_, idx2_, idy2_, idz2_;
     bool training_;
     hipStream_t s_;
     NetLayer L_[kLayers];
@@ -68,7 +70,7 @@ private:
     float* wpart_ = nullptr;
     long long wpart_floats_ = 0;
     double* red_ = nullptr;  // reduction partials
-    double* sc_ = nullptr;   // device scalars: [0] mean p_prev, [1] s, [2] loss, ...
+    double* sc_ = nullptr;   // device scalars: [0] mean p_prev, [1] s_r, [2] loss, [3] s_p
 };
 
 }  // namespace stp

@@ -83,8 +83,29 @@ __global__ __launch_bounds__(256) void k_mean_from(const double* __restrict__ pa
     if (threadIdx.x == 0) sc[0] = a / (double)n;
 }
 
-__global__ __launch_bounds__(256) void k_sumsq_pb(const double* __restrict__ p, const double* __restrict__ b, long long n,
-                                                  double invD, const double* __restrict__ sc, double* __restrict__ part)
+// L p at cell v (periodic in x, y; zero normal gradient at the walls)
+struct LapGeo {
+    int nx, ny, nz;
+    double idx2, idy2, idz2;
+};
+__device__ __forceinline__ double lap_at(const LapGeo& G, const double* __restrict__ p, long long v)
+{
+    const long long plane = (long long)G.nx * G.ny;
+    const int x = (int)(v % G.nx), y = (int)((v / G.nx) % G.ny), z = (int)(v / plane);
+    const long long row = v - x, pl = v - (long long)y * G.nx - x;
+    const double pc = p[v];
+    const double pe = p[row + (x == G.nx - 1 ? 0 : x + 1)], pw = p[row + (x == 0 ? G.nx - 1 : x - 1)];
+    const double pn = p[pl + (long long)(y == G.ny - 1 ? 0 : y + 1) * G.nx + x];
+    const double ps = p[pl + (long long)(y == 0 ? G.ny - 1 : y - 1) * G.nx + x];
+    const double pt = z + 1 < G.nz ? p[v + plane] : pc;
+    const double pb = z > 0 ? p[v - plane] : pc;
+    return (pw + pe - 2.0 * pc) * G.idx2 + (ps + pn - 2.0 * pc) * G.idy2 + ((pt - pc) + (pb - pc)) * G.idz2;
+}
+
+// partial sums of (p - mean)^2 and (r / D)^2 with r = b - L p
+__global__ __launch_bounds__(256) void k_sumsq_pr(LapGeo G, const double* __restrict__ p, const double* __restrict__ b,
+                                                  long long n, double invD, const double* __restrict__ sc,
+                                                  double* __restrict__ part)
 {
     __shared__ double lds[8];
     const double m = sc[0];
@@ -92,7 +113,7 @@ __global__ __launch_bounds__(256) void k_sumsq_pb(const double* __restrict__ p, 
     for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
         const double d = p[v] - m;
         a += d * d;
-        const double e = b[v] * invD;
+        const double e = (b[v] - lap_at(G, p, v)) * invD;
         c += e * e;
     }
     a = block_sum(a, lds);
@@ -101,7 +122,7 @@ __global__ __launch_bounds__(256) void k_sumsq_pb(const double* __restrict__ p, 
     if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = c;
 }
 
-// s = rms(p - mean), else rms(b / D), else 1
+// sc[1] = s_r = rms(r / D), sc[3] = s_p = rms(p - mean); 1 where zero
 __global__ __launch_bounds__(256) void k_scale_from(const double* __restrict__ part, long long n, double* __restrict__ sc)
 {
     __shared__ double lds[8];
@@ -113,22 +134,21 @@ __global__ __launch_bounds__(256) void k_scale_from(const double* __restrict__ p
     a = block_sum(a, lds);
     c = block_sum(c, lds);
     if (threadIdx.x == 0) {
-        double s = sqrt(a / (double)n);
-        if (s == 0.0) s = sqrt(c / (double)n);
-        if (s == 0.0) s = 1.0;
-        sc[1] = s;
+        double sp = sqrt(a / (double)n), sr = sqrt(c / (double)n);
+        sc[1] = sr == 0.0 ? 1.0 : sr;
+        sc[3] = sp == 0.0 ? 1.0 : sp;
     }
 }
 
-// X[v] = (b/(D s), (p - mean)/s, 0 x 14) in BF16
-__global__ void k_normalise(const double* __restrict__ b, const double* __restrict__ p, long long n, double invD,
-                            const double* __restrict__ sc, uint16_t* __restrict__ X)
+// X[v] = (r/(D s_r), (p - mean)/s_p, 0 x 14) in BF16
+__global__ void k_normalise(LapGeo G, const double* __restrict__ b, const double* __restrict__ p, long long n,
+                            double invD, const double* __restrict__ sc, uint16_t* __restrict__ X)
 {
-    const double m = sc[0], s = sc[1];
+    const double m = sc[0], sr = sc[1], sp = sc[3];
     for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
         uint16_t* o = X + v * 16;
-        o[0] = f2bf((float)(b[v] * invD / s));
-        o[1] = f2bf((float)((p[v] - m) / s));
+        o[0] = f2bf((float)((b[v] - lap_at(G, p, v)) * invD / sr));
+        o[1] = f2bf((float)((p[v] - m) / sp));
 #pragma unroll
         for (int c = 2; c < 16; ++c) o[c] = 0;
     }
@@ -601,8 +621,9 @@ size_t NetModel::workspace_bytes(int nx, int ny, int nz, bool training)
     return sizes(nx, ny, nz, training).total;
 }
 
-NetModel::NetModel(int nx, int ny, int nz, double D, bool training, void* ws, hipStream_t s)
-    : D_(D), training_(training), s_(s)
+NetModel::NetModel(int nx, int ny, int nz, double idx2, double idy2, double idz2, bool training, void* ws,
+                   hipStream_t s)
+    : D_(2.0 * (idx2 + idy2 + idz2)), idx2_(idx2), idy2_(idy2), idz2_(idz2), training_(training), s_(s)
 {
     const Sizes S = sizes(nx, ny, nz, training);
     for (int l = 0; l < 3; ++l) {
@@ -704,11 +725,12 @@ hipError_t NetModel::sync()
 hipError_t NetModel::normalise(const double* b, const double* p_prev)
 {
     const long long n = nv_[0];
+    const LapGeo G{nx_[0], ny_[0], nz_[0], idx2_, idy2_, idz2_};
     hipLaunchKernelGGL(k_sum_p, dim3(kRedBlocks), dim3(256), 0, s_, p_prev, n, red_);
     hipLaunchKernelGGL(k_mean_from, dim3(1), dim3(256), 0, s_, red_, n, sc_);
-    hipLaunchKernelGGL(k_sumsq_pb, dim3(kRedBlocks), dim3(256), 0, s_, p_prev, b, n, 1.0 / D_, sc_, red_);
+    hipLaunchKernelGGL(k_sumsq_pr, dim3(kRedBlocks), dim3(256), 0, s_, G, p_prev, b, n, 1.0 / D_, sc_, red_);
     hipLaunchKernelGGL(k_scale_from, dim3(1), dim3(256), 0, s_, red_, n, sc_);
-    hipLaunchKernelGGL(k_normalise, dim3(g1(n)), dim3(256), 0, s_, b, p_prev, n, 1.0 / D_, sc_, X_);
+    hipLaunchKernelGGL(k_normalise, dim3(g1(n)), dim3(256), 0, s_, G, b, p_prev, n, 1.0 / D_, sc_, X_);
     return hipGetLastError();
 }
 

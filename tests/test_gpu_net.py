@@ -60,8 +60,8 @@ def test_forward_matches_oracle(gpu, g):
             p[k] = 0.05 * r.standard_normal(p[k].shape)
     upload(ch, params, p, layout)
     b, p_prev, _ = sample(g, 7)
-    D = 2 * (g[0] / g[3]) ** 2 + 2 * (g[1] / g[4]) ** 2 + 2 * (g[2] / g[5]) ** 2
-    ref = onet.predict(p, b, p_prev, D, round_bf16=True)
+    P = oracle.make_params(*g)
+    ref = onet.predict(p, b, p_prev, oracle.lap_p(P, p_prev), oracle.diag_d(P), round_bf16=True)
     out = torch.zeros_like(to_dev(torch, b))
     ch.net_predict(to_dev(torch, b), to_dev(torch, p_prev), out)
     got = out.cpu().numpy()
@@ -82,8 +82,8 @@ def test_gradients_match_oracle(gpu, g):
             p[k] = 0.05 * r.standard_normal(p[k].shape)
     upload(ch, params, p, layout)
     b, p_prev, p_next = sample(g, 10)
-    D = 2 * (g[0] / g[3]) ** 2 + 2 * (g[1] / g[4]) ** 2 + 2 * (g[2] / g[5]) ** 2
-    x, s, _ = onet.normalise(b, p_prev, D)
+    P = oracle.make_params(*g)
+    x, s = onet.normalise(b, p_prev, oracle.lap_p(P, p_prev), oracle.diag_d(P))
     loss_ref, g_ref, _ = onet.loss_and_grads(p, x, (p_next - p_prev) / s, round_bf16=True)
     loss = ch.net_train_step(to_dev(torch, b), to_dev(torch, p_prev), to_dev(torch, p_next), 0.0)
     assert loss == pytest.approx(loss_ref, rel=5e-3)
@@ -105,8 +105,8 @@ def test_adam_steps_match_oracle_and_reduce_loss(gpu):
     p = onet.init_params(seed=11)
     upload(ch, params, p, layout)
     b, p_prev, p_next = sample(g, 12)
-    D = 2 * (g[0] / g[3]) ** 2 + 2 * (g[1] / g[4]) ** 2 + 2 * (g[2] / g[5]) ** 2
-    x, s, _ = onet.normalise(b, p_prev, D)
+    P = oracle.make_params(*g)
+    x, s = onet.normalise(b, p_prev, oracle.lap_p(P, p_prev), oracle.diag_d(P))
     t = (p_next - p_prev) / s
     state = {}
     pr = {k: v.copy() for k, v in p.items()}

@@ -84,11 +84,15 @@ def test_adam_first_step_is_sign_times_lr():
 
 
 def test_normalisation_and_prediction_identity():
-    """A zero network (all weights and biases zero) predicts p_prev exactly."""
+    """A zero network (all weights and biases zero) predicts p_prev exactly;
+    the residual channel has unit rms."""
     r = np.random.Generator(np.random.PCG64(5))
     b = r.standard_normal((8, 8, 8))
     p = r.standard_normal((8, 8, 8))
+    lap = r.standard_normal((8, 8, 8))
     params = {k: np.zeros_like(v) for k, v in net.init_params().items()}
-    np.testing.assert_array_equal(net.predict(params, b, p, 3.0), p)
-    x, s, pm = net.normalise(b, p, 3.0)
+    np.testing.assert_array_equal(net.predict(params, b, p, lap, 3.0), p)
+    x, s_r = net.normalise(b, p, lap, 3.0)
+    assert abs(np.sqrt(np.mean(x[..., 0] ** 2)) - 1.0) < 1e-12
     assert abs(np.sqrt(np.mean(x[..., 1] ** 2)) - 1.0) < 1e-12
+    np.testing.assert_allclose(x[..., 0] * s_r * 3.0, b - lap, atol=1e-12)
