@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "pressure-relax Gcell-updates/s + %HBM peak; LES steps/s, learned vs plain"
+FIXED_CYCLES = False  # set by --fixed-cycles: repeat the 1e-3 cycle instead of sizing cycles adaptively
 
 
 def parse():
@@ -36,6 +37,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start run")
+    ap.add_argument("--fixed-cycles", action="store_true", help="repeat the fixed 1e-3 SRJ cycle (no adaptive sizing)")
     ap.add_argument("--sweeps", type=int, default=200, help="sweeps in the kernel roofline timing")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run a plain copy of known size and the relaxation kernels (for rocprofv3 counters)")
@@ -47,7 +49,7 @@ def make_channel(wl, precision, rtol, warm_start=0):
     from paper_1511_07800_amd import Channel, inputs
     ch = Channel(wl["nx"], wl["ny"], wl["nz"], wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"],
                  dt=wl["dt"], les=wl["les"], cs=wl.get("cs", 0.1), vd_a=wl.get("vd_a", 25.0), precision=precision,
-                 poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start)
+                 poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=0 if FIXED_CYCLES else 1)
     u, v, w = inputs.channel_state(wl["nx"], wl["ny"], wl["nz"], wl["lz"], wl["nu"], wl["dpdx"],
                                    noise=wl.get("noise", 0.0), seed=wl.get("seed", 0))
     for k, a in enumerate((u, v, w)):
@@ -164,6 +166,8 @@ def cpu_baseline(wl, seconds=12.0):
 
 def main():
     args = parse()
+    global FIXED_CYCLES
+    FIXED_CYCLES = args.fixed_cycles
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design note, not an implementation.", file=sys.stderr)
@@ -196,19 +200,26 @@ def main():
         torch.cuda.empty_cache()
 
     learned = None
+    learned_256 = None
     if not args.no_learned:
         from paper_1511_07800_amd import STP_WS_LEARNED, warmstart
-        ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED)
-        ch.net_init(training=False)
-        warmstart.load_weights(ch)
-        tl, accl, stl = time_steps(ch, args.steps, args.warmup, "learned+mixed")
-        learned = {"steps_per_s": round(args.steps / tl, 4), "ms_per_step": round(1e3 * tl / args.steps, 2),
+
+        def run_learned(weights, label):
+            ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED)
+            ch.net_init(training=False)
+            warmstart.load_weights(ch, weights)
+            tl, accl, stl = time_steps(ch, args.steps, args.warmup, label)
+            out = {"steps_per_s": round(args.steps / tl, 4), "ms_per_step": round(1e3 * tl / args.steps, 2),
                    "sweeps_per_step": accl["sweeps"] / args.steps, "ms_net_last": round(stl["ms_net"], 2),
                    "relres_prev_last": stl["relres_prev"], "relres_learned_last": stl["relres_learned"],
-                   "weights": "paper_1511_07800_amd/weights/warmstart_les.npy (trained on 256x128x128 triples)"}
-        ch.close()
-        del ch
-        torch.cuda.empty_cache()
+                   "weights": os.path.relpath(weights, ROOT)}
+            ch.close()
+            torch.cuda.empty_cache()
+            return out
+
+        wdir = os.path.join(ROOT, "paper_1511_07800_amd", "weights")
+        learned = run_learned(os.path.join(wdir, "warmstart_les512.npy"), "learned+mixed")
+        learned_256 = run_learned(os.path.join(wdir, "warmstart_les.npy"), "learned(256-trained)+mixed")
 
     roof = roofline_from_steps(n, acc_mixed, 4, "k_relax_fused<float,4,8>")
     roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
@@ -221,7 +232,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": [wl["nx"], wl["ny"], wl["nz"]], "precision": "mixed",
-                   "poisson_rtol": args.rtol, "dt": wl["dt"], "les": wl["les"], "init": "laminar+10% noise"},
+                   "poisson_rtol": args.rtol, "dt": wl["dt"], "les": wl["les"], "init": "laminar+10% noise",
+                   "srj_cycles": "fixed 1e-3" if FIXED_CYCLES else "adaptive"},
         "les_steps_per_s": {"mixed": round(args.steps / t_mixed, 4), "fp64": fp64["steps_per_s"] if fp64 else None,
                             "learned_mixed": learned["steps_per_s"] if learned else None},
         "sweeps_per_step": {"mixed": acc_mixed["sweeps"] / args.steps,
@@ -229,6 +241,7 @@ def main():
                             "learned_mixed": learned["sweeps_per_step"] if learned else None},
         "fp64": fp64,
         "learned_mixed": learned,
+        "learned_mixed_trained_256x128x128": learned_256,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -106,6 +106,8 @@ typedef struct {
     const double* srj_omega;   /* host array of srj_m weights in sweep order (copied at init) */
     double srj_reduction;      /* built-in schedule: bound on one cycle's error reduction (e.g. 1e-3) */
     int32_t mixed_inner;       /* mixed mode: FP32 cycles per defect-correction pass (>= 1) */
+    int32_t srj_adaptive;      /* built-in schedule only: 0 repeats the srj_reduction cycle; 1 sizes each
+                                  cycle from the reduction still needed (see stp_poisson_solve) */
     int32_t tblock;            /* sweeps fused per relaxation launch: 1, 2 or 4 (0 selects 4); grids with
                                   nx < 64 or ny < 32 always run single sweeps.  Results are bitwise
                                   identical for every value. */
@@ -164,6 +166,12 @@ stp_status stp_step(stp_ctx* ctx, int32_t nsteps, stp_step_stats* last);
 
 /* Solve L_p p = b (Sec. 3.1 Poisson equation, zero normal gradient at the
  * walls, periodic in x and y) with the context's schedule and precision.
+ * With srj_adaptive = 1 each cycle is a Chebyshev/Leja cycle whose degree M
+ * (rounded up to a multiple of 16) meets the bound 1/T_M <= rho on the residual
+ * reduction, rho = max(rtol ||b|| / (2 ||r||), floor), floor = 1e-10 in FP64 and
+ * srj_reduction for the FP32 passes of the mixed mode; a cycle of degree M
+ * multiplies every residual mode by at most 1/T_M, so one cycle usually meets
+ * the test.
  * b_dev: device FP64 array of nx*ny*nz values, mean-free (borrowed, read).
  * p_dev: device FP64 array, initial guess in, solution out (mean removed).
  * rtol, maxit as in stp_config.  stats nullable.  Returns STP_OK,

@@ -149,6 +149,34 @@ def poisson_srj(P, b, p0, omega, rtol, maxit):
     return p, st, cyc.value, r0.value, r1.value
 
 
+def poisson_srj_adaptive(P, b, p0, rtol, maxit, floor=1e-10):
+    """SRJ solve whose every cycle is sized from the reduction still needed
+    (schedule.adaptive_degree); returns (p, status, cycles, sweeps, relres0, relres)."""
+    from .schedule import kappa_bounds as kb, adaptive_degree, schedule_of_degree
+    a, bb = kb(P.nx, P.ny, P.nz, P.lx, P.ly, P.lz)
+    p = np.array(p0, dtype=np.float64, order="C", copy=True)
+    bn = float(np.sqrt(np.sum(b * b)))
+    fb = bn if bn > 1e-300 else 1e-300
+    rn = float(np.sqrt(residual(P, p, b)[1]))
+    relres0 = rn / fb
+    cycles = sweeps = 0
+    status = 0
+    while not (rn <= rtol * fb):
+        if not np.isfinite(rn):
+            status = -5
+            break
+        if cycles >= maxit:
+            status = -4
+            break
+        om = schedule_of_degree(a, bb, adaptive_degree(a, bb, rtol, fb, rn, floor))
+        p, _, _, _, _ = poisson_srj(P, b, p, om, 0.0, 1)
+        cycles += 1
+        sweeps += len(om)
+        rn = float(np.sqrt(residual(P, p, b)[1]))
+    p -= p.mean()
+    return p, status, cycles, sweeps, relres0, rn / fb
+
+
 def divergence(P, u, v, w):
     out = np.empty(cell_shape(P))
     lib().or_divergence(ctypes.byref(P), _p(u), _p(v), _p(w), _p(out))

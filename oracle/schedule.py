@@ -81,6 +81,21 @@ def srj_schedule(nx, ny, nz, lx, ly, lz, reduction=1e-3):
     return 1.0 / leja_order(chebyshev_nodes(a, b, m))
 
 
+def schedule_of_degree(a, b, m):
+    return 1.0 / leja_order(chebyshev_nodes(a, b, m))
+
+
+def adaptive_degree(a, b, rtol, bnorm, rnorm, floor):
+    """Cycle degree for a pass that must reduce the residual from rnorm to
+    rtol * bnorm: rho = max(rtol bnorm / (2 rnorm), floor) capped at 1/2; the
+    least degree with 1/T_M <= rho, rounded up to a multiple of 16.  (One
+    cycle multiplies every residual mode by at most 1/T_M, so the 2-norm of the
+    residual shrinks by at least that factor.)"""
+    rho = min(0.5, max(floor, 0.5 * rtol * bnorm / rnorm))
+    m = chebyshev_degree(a, b, rho)
+    return (m + 15) // 16 * 16
+
+
 def cycle_factor(omega, kappa):
     """prod_k (1 - omega_k kappa): one cycle's effect on a mode."""
     g = np.ones_like(np.asarray(kappa, dtype=np.float64))

@@ -28,7 +28,8 @@ class Config(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("poisson_rtol", ctypes.c_double), ("poisson_maxit", ctypes.c_int32),
                 ("srj_m", ctypes.c_int32), ("srj_omega", ctypes.POINTER(ctypes.c_double)),
-                ("srj_reduction", ctypes.c_double), ("mixed_inner", ctypes.c_int32), ("tblock", ctypes.c_int32),
+                ("srj_reduction", ctypes.c_double), ("mixed_inner", ctypes.c_int32),
+                ("srj_adaptive", ctypes.c_int32), ("tblock", ctypes.c_int32),
                 ("cn_tol", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
@@ -124,7 +125,8 @@ class Channel:
 
     def __init__(self, nx, ny, nz, lx, ly, lz, nu, dpdx, dt, les=0, cs=0.1, vd_a=25.0,
                  precision=STP_FP64, warm_start=STP_WS_PREV, poisson_rtol=1e-10, poisson_maxit=1000,
-                 omega=None, srj_reduction=1e-3, mixed_inner=1, tblock=4, cn_tol=1e-13, device=None):
+                 omega=None, srj_reduction=1e-3, mixed_inner=1, tblock=4, cn_tol=1e-13, srj_adaptive=0,
+                 device=None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -146,6 +148,7 @@ class Channel:
             cfg.srj_m = 0
             cfg.srj_omega = None
         cfg.srj_reduction, cfg.mixed_inner, cfg.tblock, cfg.cn_tol = srj_reduction, mixed_inner, tblock, cn_tol
+        cfg.srj_adaptive = srj_adaptive
         cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.cfg = cfg
         nbytes = self.lib.stp_workspace_bytes(ctypes.byref(cfg))

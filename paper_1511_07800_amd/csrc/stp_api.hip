@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -31,6 +32,8 @@ struct stp_ctx {
     double* res = nullptr;   // device scalar results
     double* host = nullptr;  // pinned host copy of res
     std::vector<double> omega;  // the relaxation cycle (weights)
+    double kmin = 0.0, kmax = 0.0;                     // spectrum of L_p / D
+    std::map<int, std::vector<double>> cycles;        // adaptive cycles by degree
     double D = 0.0;             // Jacobi diagonal 2/dx^2 + 2/dy^2 + 2/dz^2
     int step = 0;
     stp::NetModel* net = nullptr;
@@ -82,6 +85,8 @@ const char* validate(const stp_config& c)
         return "srj_reduction must lie in (0, 1)";
     }
     if (c.mixed_inner < 1) return "mixed_inner must be >= 1";
+    if (c.srj_adaptive != 0 && c.srj_adaptive != 1) return "srj_adaptive must be 0 or 1";
+    if (c.srj_adaptive && c.srj_m > 0) return "srj_adaptive needs the built-in schedule (srj_m = 0)";
     if (c.tblock != 1 && c.tblock != 2 && c.tblock != 4) return "tblock must be 1, 2 or 4";
     if (!(c.cn_tol > 0.0 && c.cn_tol < 1.0)) return "cn_tol must lie in (0, 1)";
     return nullptr;
@@ -153,10 +158,14 @@ void kappa_range(const Geo& g, double D, double* kmin, double* kmax)
     *kmax = lmax / D;
 }
 
-std::vector<double> chebyshev_leja_cycle(double a, double b, double reduction)
+int chebyshev_degree(double a, double b, double reduction)
 {
     const double s = (b + a) / (b - a);
-    const int m = std::max(1, (int)std::ceil(std::acosh(1.0 / reduction) / std::acosh(s)));
+    return std::max(1, (int)std::ceil(std::acosh(1.0 / reduction) / std::acosh(s)));
+}
+
+std::vector<double> chebyshev_leja_nodes(double a, double b, int m)
+{
     std::vector<double> x(m);
     for (int k = 1; k <= m; ++k) x[k - 1] = 0.5 * (a + b) + 0.5 * (b - a) * std::cos(M_PI * (2.0 * k - 1.0) / (2.0 * m));
     // Leja order: largest magnitude first, then maximise the product of
@@ -190,6 +199,11 @@ std::vector<double> chebyshev_leja_cycle(double a, double b, double reduction)
     return out;
 }
 
+std::vector<double> chebyshev_leja_cycle(double a, double b, double reduction)
+{
+    return chebyshev_leja_nodes(a, b, chebyshev_degree(a, b, reduction));
+}
+
 #define CHK(expr)                                                                   \
     do {                                                                            \
         hipError_t e_ = (expr);                                                     \
@@ -208,6 +222,21 @@ stp_status readback(stp_ctx* ctx)
 
 // Run `count` sweeps of the schedule starting at sweep index `first` (mod M),
 // ping-ponging between *cur and *other; on return *cur holds the iterate.
+// The cycle for the next pass: the fixed cycle, or (adaptive) the Chebyshev/
+// Leja cycle whose degree, rounded up to a multiple of 16, bounds the residual
+// reduction by rho = max(rtol ||b|| / (2 ||r||), floor), rho <= 1/2.
+const std::vector<double>& next_cycle(stp_ctx* ctx, double rtol, double fb, double rn, double floor_rho)
+{
+    if (!ctx->cfg.srj_adaptive || !(rtol > 0.0) || !(rn > 0.0)) return ctx->omega;
+    double rho = 0.5 * rtol * fb / rn;
+    rho = std::min(0.5, std::max(floor_rho, rho));
+    int m = chebyshev_degree(ctx->kmin, ctx->kmax, rho);
+    m = (m + 15) / 16 * 16;
+    auto it = ctx->cycles.find(m);
+    if (it == ctx->cycles.end()) it = ctx->cycles.emplace(m, chebyshev_leja_nodes(ctx->kmin, ctx->kmax, m)).first;
+    return it->second;
+}
+
 template <typename T>
 stp_status run_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, const double* omega, int m, long long first,
                       long long count, int* launches = nullptr)
@@ -232,11 +261,11 @@ stp_status run_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, const double
 // run_sweeps between two events; adds the device time to st->ms_relax after
 // the next synchronisation (timed_flush).
 template <typename T>
-stp_status timed_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, long long count, stp_solve_stats* st)
+stp_status timed_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, const std::vector<double>& omega, long long count,
+                        stp_solve_stats* st)
 {
     CHK(hipEventRecord(ctx->ev[4], ctx->s));
-    stp_status rc = run_sweeps<T>(ctx, b, cur, other, ctx->omega.data(), (int)ctx->omega.size(), 0, count,
-                                  &st->launches);
+    stp_status rc = run_sweeps<T>(ctx, b, cur, other, omega.data(), (int)omega.size(), 0, count, &st->launches);
     if (rc != STP_OK) return rc;
     CHK(hipEventRecord(ctx->ev[5], ctx->s));
     return STP_OK;
@@ -268,11 +297,14 @@ stp_status solve_fp64(stp_ctx* ctx, const double* b, double* p, double* ptmp, do
     st->relres0 = rn / fb;
     st->status = STP_OK;
     int cycles = 0, checks = 0;
+    long long sweeps = 0;
     if (rtol > 0.0) {
         while (!(rn <= rtol * fb)) {
             if (!std::isfinite(rn)) { st->status = STP_ENAN; break; }
             if (cycles >= maxit) { st->status = STP_ENOCONV; break; }
-            if ((rc = timed_sweeps<double>(ctx, b, &cur, &oth, m, st)) != STP_OK) return rc;
+            const std::vector<double>& cyc = next_cycle(ctx, rtol, fb, rn, 1e-10);
+            if ((rc = timed_sweeps<double>(ctx, b, &cur, &oth, cyc, (long long)cyc.size(), st)) != STP_OK) return rc;
+            sweeps += (long long)cyc.size();
             ++cycles;
             CHK(residual(ctx->g, b, cur, nullptr, ctx->part, ctx->res, ctx->s));
             if ((rc = readback(ctx)) != STP_OK) return rc;
@@ -281,7 +313,8 @@ stp_status solve_fp64(stp_ctx* ctx, const double* b, double* p, double* ptmp, do
             ++checks;
         }
     } else {
-        if ((rc = timed_sweeps<double>(ctx, b, &cur, &oth, (long long)m * maxit, st)) != STP_OK) return rc;
+        if ((rc = timed_sweeps<double>(ctx, b, &cur, &oth, ctx->omega, (long long)m * maxit, st)) != STP_OK) return rc;
+        sweeps = (long long)m * maxit;
         cycles = maxit;
         CHK(residual(ctx->g, b, cur, nullptr, ctx->part, ctx->res, ctx->s));
         if ((rc = readback(ctx)) != STP_OK) return rc;
@@ -296,7 +329,7 @@ stp_status solve_fp64(stp_ctx* ctx, const double* b, double* p, double* ptmp, do
     st->relres = rn / fb;
     st->cycles = cycles;
     st->outer = checks;
-    st->sweeps = cycles * m;
+    st->sweeps = (int32_t)sweeps;
     return STP_OK;
 }
 
@@ -304,7 +337,6 @@ stp_status solve_fp64(stp_ctx* ctx, const double* b, double* p, double* ptmp, do
 // e = 0, FP64 update p += e, repeated until the FP64 residual test passes.
 stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, int maxit, stp_solve_stats* st)
 {
-    const int m = (int)ctx->omega.size();
     const int inner = ctx->cfg.mixed_inner;
     stp_status rc;
     CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s));
@@ -316,11 +348,15 @@ stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, in
     st->relres0 = rn / fb;
     st->status = STP_OK;
     int outer = 0;
+    long long sweeps = 0;
     auto pass = [&]() -> stp_status {
         float* cur = ctx->e0;
         float* oth = ctx->e1;
         CHK(fill(cur, 0.0f, ctx->g.n, ctx->s));
-        stp_status r2 = timed_sweeps<float>(ctx, ctx->r32, &cur, &oth, (long long)m * inner, st);
+        const std::vector<double>& cyc = rtol > 0.0 ? next_cycle(ctx, rtol, fb, rn, ctx->cfg.srj_reduction) : ctx->omega;
+        const long long count = (long long)cyc.size() * inner;
+        sweeps += count;
+        stp_status r2 = timed_sweeps<float>(ctx, ctx->r32, &cur, &oth, cyc, count, st);
         if (r2 != STP_OK) return r2;
         CHK(add_correction(p, cur, ctx->g.n, ctx->s));
         CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s));
@@ -348,7 +384,7 @@ stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, in
     st->relres = rn / fb;
     st->cycles = outer * inner;
     st->outer = outer;
-    st->sweeps = outer * inner * m;
+    st->sweeps = (int32_t)sweeps;
     return STP_OK;
 }
 
@@ -548,6 +584,8 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
             delete ctx;
             return STP_EINVAL;
         }
+        ctx->kmin = a;
+        ctx->kmax = b;
         ctx->omega = chebyshev_leja_cycle(a, b, c.srj_reduction);
     }
     if (hipGetDevice(&ctx->device) != hipSuccess || hipHostMalloc((void**)&ctx->host, RES_COUNT * sizeof(double)) != hipSuccess) {

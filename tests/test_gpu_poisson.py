@@ -244,3 +244,42 @@ def test_solve_with_fused_sweeps_bitwise(gpu, precision):
         out.append((stats["cycles"], pd.cpu()))
     assert out[0][0] == out[1][0]
     assert torch.equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("g", [GRIDS[0], GRIDS[1], (96, 40, 24, 4.0, 2.0, 2.0)])
+def test_adaptive_solve_matches_oracle(gpu, g):
+    """Cycles sized from the reduction still needed: same cycles and sweeps as
+    the oracle's adaptive solve, solution within 1e-10."""
+    import torch
+    P = oracle.make_params(*g)
+    b = inputs.poisson_rhs(g[0], g[1], g[2], seed=22)
+    p0 = 0.1 * inputs.rng(23).standard_normal(b.shape)
+    p_ref, st, cyc, sweeps, r0, r1 = oracle.poisson_srj_adaptive(P, b, p0, 1e-10, 20)
+    ch = channel(g, srj_adaptive=1)
+    pd = to_dev(torch, p0)
+    stats, rc = ch.poisson_solve(to_dev(torch, b), pd, 1e-10, 20)
+    assert rc == 0 and st == 0
+    assert stats["cycles"] == cyc and stats["sweeps"] == sweeps
+    assert rel_l2(pd.cpu().numpy(), p_ref) <= 1e-10
+
+
+def test_adaptive_mixed_solve_reaches_tolerance(gpu):
+    import torch
+    from paper_1511_07800_amd import STP_MIXED
+    g = (130, 64, 40, 4.0, 2.0, 2.0)
+    P = oracle.make_params(*g)
+    om = osched.srj_schedule(*g)
+    b = inputs.poisson_rhs(g[0], g[1], g[2], seed=24)
+    p_ref, *_ = oracle.poisson_srj(P, b, np.zeros_like(b), om, 1e-12, 100)
+    fixed = channel(g, precision=STP_MIXED)
+    adapt = channel(g, precision=STP_MIXED, srj_adaptive=1)
+    out = {}
+    for name, ch in (("fixed", fixed), ("adaptive", adapt)):
+        pd = torch.zeros_like(to_dev(torch, b))
+        stats, rc = ch.poisson_solve(to_dev(torch, b), pd, 1e-9, 50)
+        assert rc == 0 and stats["relres"] <= 1e-9
+        assert rel_l2(pd.cpu().numpy(), p_ref) <= 1e-5
+        out[name] = stats["sweeps"]
+    print("mixed sweeps to 1e-9:", out)
+    # cycle degrees are rounded up to multiples of 16: allow that slack on a small grid
+    assert out["adaptive"] <= 1.1 * out["fixed"]

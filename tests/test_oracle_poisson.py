@@ -257,3 +257,22 @@ def test_residual_reduction_per_cycle_bounded():
         cur = math.sqrt(oracle.residual(P, p, b)[1])
         assert cur <= 2e-3 * prev
         prev = cur
+
+
+def test_adaptive_cycles_reach_tolerance_and_match_direct_solve():
+    """Sizing each cycle from the reduction still needed: the residual bound of
+    one cycle (1/T_M per mode) makes a single cycle enough from any start."""
+    g = (32, 16, 16, 2 * math.pi, math.pi, 2.0)
+    P = oracle.make_params(*g)
+    b = inputs.poisson_rhs(32, 16, 16, seed=21)
+    p, st, cyc, sweeps, r0, r1 = oracle.poisson_srj_adaptive(P, b, np.zeros_like(b), 1e-10, 10)
+    assert st == 0 and r1 <= 1e-10 and cyc == 1
+    ref = separable_direct_solve(g, b)
+    assert np.abs(p - ref).max() <= 1e-7 * np.abs(ref).max()
+    a, bb = srj_schedule.kappa_bounds(*g)
+    m = srj_schedule.adaptive_degree(a, bb, 1e-10, 1.0, 1.0, 1e-10)
+    assert m % 16 == 0 and sweeps == m
+    # the fixed 1e-3 cycle needs more sweeps for the same tolerance
+    om = srj_schedule.srj_schedule(*g)
+    _, _, cyc_f, _, _ = oracle.poisson_srj(P, b, np.zeros_like(b), om, 1e-10, 100)
+    assert cyc_f * len(om) > sweeps
