@@ -249,7 +249,7 @@ stp_status run_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, const double
         const long long left = count - s;
         const int nf = left >= tb ? tb : (left >= 2 && tb >= 2 ? 2 : 1);
         Weights wts{};
-        for (int f = 0; f < nf; ++f) wts.c[f] = omega[(first + s + f) % m] / ctx->D;
+        for (int f = 0; f < nf; ++f) wts.omega[f] = omega[(first + s + f) % m];
         CHK(relax<T>(ctx->g, b, *cur, *other, wts, nf, ctx->s));
         std::swap(*cur, *other);
         s += nf;

@@ -42,8 +42,8 @@ enum ResSlot {
 constexpr int kMaxPartBlocks = 65536;  // partial-sum slots per reduced quantity
 constexpr int kMaxFused = 4;           // sweeps fused per relaxation launch
 
-struct Weights {  // omega_s / D for the fused sweeps of one launch
-    double c[kMaxFused];
+struct Weights {  // omega_s of the fused sweeps of one launch
+    double omega[kMaxFused];
 };
 
 // ---- launchers (all enqueue on `s`, return hipError of the launch) ----

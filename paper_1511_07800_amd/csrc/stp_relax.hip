@@ -1,19 +1,25 @@
 // Temporally blocked Jacobi-SOR sweeps for gfx950 (Sec. 3.4: the SRJ cycle
 // is a sequence of weighted Jacobi sweeps p <- p + (omega_s/D)(L_p p - b)).
 //
-// The sweep is HBM-bound (about one flop per byte), so NT consecutive sweeps
-// of the cycle are fused into one launch: every workgroup owns a 64 x 32
-// column tile of the x-y plane (periodic wrap computed in-kernel) and marches
-// along z.  At each z step it loads one plane of p and b, then advances every
-// stage s = 1..NT of the pipeline by one plane: stage s produces plane t - s
-// from stage s-1's planes t-s-1, t-s, t-s+1.  The vertical neighbours live in
-// per-thread register rings, the x-y neighbours in one LDS plane per stage.
-// Stage s is exact on points at least s away from the tile edge, so a tile
-// writes its central (64 - 2NT) x (32 - 2NT) columns; a z-chunk is extended
-// by NT planes on each side (clipped at the walls, where the zero-gradient
-// ghost equals the centre value).  Each point evaluates exactly the unblocked
-// formula in the same order, so NT fused sweeps equal NT single sweeps bit
-// for bit.
+// NT consecutive sweeps of the cycle are fused into one launch: every
+// workgroup owns a 64 x 32 column tile of the x-y plane (periodic wrap
+// computed in-kernel) and marches along z.  At each z step it loads one plane
+// of p and b, then advances every stage s = 1..NT of the pipeline by one
+// plane: stage s produces plane t - s from stage s-1's planes t-s-1, t-s,
+// t-s+1.  The vertical neighbours live in per-thread register rings, the x-y
+// neighbours in one LDS plane per stage.  Stage s is exact on points at least
+// s away from the tile edge, so a tile writes its central (64 - 2NT) x
+// (32 - 2NT) columns; a z-chunk is extended by NT planes on each side
+// (clipped at the walls).  Each point evaluates exactly the unblocked formula
+// (sweep_point) in the same order, so NT fused sweeps equal NT single sweeps
+// bit for bit.
+//
+// With HBM traffic cut by NT, the kernel is bound by vector-ALU issue and by
+// load latency along the march, which shape the code: the point update is
+// eight instructions, a stage skips (per wavefront) the rows and planes that
+// no later stage reads, the wall ghosts are stored in the rings instead of
+// selected per point, loads are addressed as a 32-bit lane offset on a
+// uniform plane base, and the next plane is requested one step ahead.
 #include "stp_internal.h"
 
 #include <algorithm>
@@ -29,12 +35,93 @@ static int kTargetBlocks = 2048;  // workgroups to aim for
 #ifndef STP_RELAX_WAVES
 #define STP_RELAX_WAVES 8      // wavefronts per workgroup; kTileY / waves rows per thread
 #endif
+#ifndef STP_RELAX_PF
+#define STP_RELAX_PF 1         // planes of p and b requested ahead of the one processed
+#endif
+constexpr int PF = STP_RELAX_PF;
+
+// Coefficients of one weighted Jacobi sweep, from omega and D = 2/dx^2 +
+// 2/dy^2 + 2/dz^2:  p + (omega/D)(L_p p - b)
+//   = (1 - omega) p + kx (pw + pe) + ky (ps + pn) + kz (pt + pb) - kb b,
+// kx = omega/(D dx^2), ky = omega/(D dy^2), kz = omega/(D dz^2), kb = omega/D:
+// the relaxation (1 - omega) p + omega J(p) of the plain Jacobi update J.
+struct StageCoefs {
+    double k0[kMaxFused], kx[kMaxFused], ky[kMaxFused], kz[kMaxFused], kb[kMaxFused];
+};
+
+StageCoefs stage_coefs(const Geo& g, const Weights& w, int n)
+{
+    const double D = 2.0 * (g.idx2 + g.idy2 + g.idz2);
+    StageCoefs k{};
+    for (int s = 0; s < n; ++s) {
+        const double kb = w.omega[s] / D;
+        k.k0[s] = 1.0 - w.omega[s];
+        k.kx[s] = kb * g.idx2;
+        k.ky[s] = kb * g.idy2;
+        k.kz[s] = kb * g.idz2;
+        k.kb[s] = kb;
+    }
+    return k;
+}
+
+template <typename T>
+struct Coef {
+    T k0, kx, ky, kz, kb;
+};
+
+template <typename T>
+__device__ __forceinline__ T fma_(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// One weighted Jacobi update of a cell from its six neighbours (zero-gradient
+// ghosts already substituted), with explicit fused multiply-adds in a fixed
+// order so the single-sweep and the fused kernels round identically: three
+// adds, one multiply, four fused multiply-adds.
+template <typename T>
+__device__ __forceinline__ T sweep_point(const Coef<T>& k, T pw, T pe, T ps, T pn, T pt, T pb, T pc, T bb)
+{
+    T acc = fma_(-k.kb, bb, k.k0 * pc);
+    acc = fma_(k.kx, pw + pe, acc);
+    acc = fma_(k.ky, ps + pn, acc);
+    return fma_(k.kz, pt + pb, acc);
+}
+
+// Buffer-resource access: a uniform plane base in scalar registers, a 32-bit
+// per-lane byte offset, and the plane size as the range (out-of-range loads
+// return zero, stores are dropped).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
 
 template <typename T, int NT, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_relax_fused(int nx, int ny, int nz, int zchunk,
                                                             const T* __restrict__ b, const T* __restrict__ p,
-                                                            T* __restrict__ out, Weights wts, T idx2, T idy2,
-                                                            T idz2)
+                                                            T* __restrict__ out, StageCoefs kc)
 {
     constexpr int PTS = kTileY / WAVES;  // rows per thread
     constexpr int OX = kTileX - 2 * NT, OY = kTileY - 2 * NT;
@@ -46,23 +133,26 @@ __global__ __launch_bounds__(64 * WAVES) void k_relax_fused(int nx, int ny, int 
     const int y0 = blockIdx.y * OY - NT;
     const int z0 = blockIdx.z * zchunk, z1 = min(nz, z0 + zchunk);
     const long long plane = (long long)nx * ny;
+    const unsigned pbytes = (unsigned)(plane * (long long)sizeof(T));
 
     // global offsets of this thread's columns (periodic wrap)
     const int gx = ((x0 + lane) % nx + nx) % nx;
-    int col[PTS];  // offset within a plane (nx*ny < 2^31)
+    // byte offset of this thread's column within a plane: a 32-bit vector
+    // offset on a uniform plane address (planes below 4 GiB)
+    unsigned col[PTS];
     int row[PTS];
 #pragma unroll
     for (int m = 0; m < PTS; ++m) {
         row[m] = wave + WAVES * m;
         const int gy = ((y0 + row[m]) % ny + ny) % ny;
-        col[m] = gy * nx + gx;
+        col[m] = (unsigned)(gy * nx + gx) * (unsigned)sizeof(T);
     }
     const int xm = max(lane - 1, 0), xp = min(lane + 1, kTileX - 1);
     const bool out_x = lane >= NT && lane < kTileX - NT && x0 + lane < nx;
 
-    T c[NT];
+    Coef<T> c[NT];
 #pragma unroll
-    for (int s = 0; s < NT; ++s) c[s] = (T)wts.c[s];
+    for (int s = 0; s < NT; ++s) c[s] = Coef<T>{(T)kc.k0[s], (T)kc.kx[s], (T)kc.ky[s], (T)kc.kz[s], (T)kc.kb[s]};
 
     // rings: R[s][0] newest plane of stage s, R[s][1] the one before, R[s][2] before that
     T R[NT][3][PTS];
@@ -76,62 +166,101 @@ __global__ __launch_bounds__(64 * WAVES) void k_relax_fused(int nx, int ny, int 
 #pragma unroll
         for (int m = 0; m < PTS; ++m) B[s][m] = T(0);
 
+    // Plane t + PF is requested while plane t is processed, into a register
+    // slot chosen statically (the loop is unrolled by PF), so PF planes of
+    // loads stay in flight across the barriers instead of one load latency
+    // being exposed per z step.  Planes past the top wall are clamped to
+    // nz - 1, which is the zero-gradient ghost plane of stage 0.
+    T Pq[PF][PTS], Bq[PF][PTS];
     const int t_begin = max(0, z0 - NT);
     const int t_end = z1 - 1 + NT;  // the final stage reaches plane z1 - 1
-    for (int t = t_begin; t <= t_end; ++t) {
-        // stage 0: load plane t of p and b
-        const T* __restrict__ pt_plane = p + plane * t;
-        const T* __restrict__ bt_plane = b + plane * t;
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+        const long long o = plane * min(t_begin + d, nz - 1);
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(p + o, pbytes), rb = plane_rsrc(b + o, pbytes);
 #pragma unroll
         for (int m = 0; m < PTS; ++m) {
-            R[0][2][m] = R[0][1][m];
-            R[0][1][m] = R[0][0][m];
-#pragma unroll
-            for (int s = NT; s > 0; --s) B[s][m] = B[s - 1][m];
-            if (t < nz) {
-                R[0][0][m] = pt_plane[col[m]];
-                B[0][m] = bt_plane[col[m]];
-            }
+            Pq[d][m] = buf_load<T>(rp, col[m]);
+            Bq[d][m] = buf_load<T>(rb, col[m]);
         }
-        // stages 1..NT: stage s produces plane q = t - s
+    }
+    for (int tb = t_begin; tb <= t_end; tb += PF) {
 #pragma unroll
-        for (int s = 1; s <= NT; ++s) {
-            const int q = t - s;
-            T res[PTS];
+        for (int d = 0; d < PF; ++d) {
+            const int t = tb + d;
+            if (t > t_end) break;
+            // stage 0: plane t from its slot, which then requests plane t + PF
+            const long long o = plane * min(t + PF, nz - 1);
+            const __amdgpu_buffer_rsrc_t rp = plane_rsrc(p + o, pbytes), rb = plane_rsrc(b + o, pbytes);
 #pragma unroll
             for (int m = 0; m < PTS; ++m) {
-                const T pc = R[s - 1][1][m];
-                const T pt = q + 1 < nz ? R[s - 1][0][m] : pc;
-                const T pb = q > 0 ? R[s - 1][2][m] : pc;
-                const int r = row[m];
-                const int ym = max(r - 1, 0), yp = min(r + 1, kTileY - 1);
-                const T lap = (lds[s - 1][r][xm] + lds[s - 1][r][xp] - T(2) * pc) * idx2 +
-                              (lds[s - 1][ym][lane] + lds[s - 1][yp][lane] - T(2) * pc) * idy2 +
-                              ((pt - pc) + (pb - pc)) * idz2;
-                res[m] = pc + c[s - 1] * (lap - B[s][m]);
-            }
-            if (s < NT) {
+                R[0][2][m] = R[0][1][m];
+                R[0][1][m] = R[0][0][m];
+                R[0][0][m] = Pq[d][m];
 #pragma unroll
-                for (int m = 0; m < PTS; ++m) {
-                    R[s][2][m] = R[s][1][m];
-                    R[s][1][m] = R[s][0][m];
-                    R[s][0][m] = res[m];
-                }
-            } else if (q >= z0 && q < z1 && out_x) {
-                T* __restrict__ oq = out + plane * q;
+                for (int s = NT; s > 0; --s) B[s][m] = B[s - 1][m];
+                B[0][m] = Bq[d][m];
+                Pq[d][m] = buf_load<T>(rp, col[m]);
+                Bq[d][m] = buf_load<T>(rb, col[m]);
+            }
+            // Zero-gradient walls: every ring holds, in place of plane -1 and
+            // plane nz, a copy of plane 0 and plane nz - 1 of its stage, so
+            // the point update needs no select.  Stage 0 gets plane nz - 1
+            // again from the clamped loads, plane -1 here.
+            if (t == 0) {
 #pragma unroll
-                for (int m = 0; m < PTS; ++m) {
-                    const int r = row[m];
-                    if (r >= NT && r < kTileY - NT && y0 + r < ny) oq[col[m]] = res[m];
+                for (int m = 0; m < PTS; ++m) R[0][1][m] = R[0][0][m];
+            }
+            // stages 1..NT: stage s produces plane q = t - s.  Stage s is
+            // needed only on rows [s, 32 - s) and planes [z0 - (NT - s),
+            // z1 + (NT - s)) inside the walls; both tests are uniform per
+            // wavefront, so skipped rows and planes cost no issue slots.
+#pragma unroll
+            for (int s = 1; s <= NT; ++s) {
+                const int q = t - s;
+                T res[PTS];
+                if (q >= max(0, z0 - (NT - s)) && q <= min(nz - 1, z1 - 1 + (NT - s))) {
+#pragma unroll
+                    for (int m = 0; m < PTS; ++m) {
+                        const int r = row[m];
+                        res[m] = R[s - 1][1][m];
+                        if (r < s || r >= kTileY - s) continue;
+                        res[m] = sweep_point<T>(c[s - 1], lds[s - 1][r][xm], lds[s - 1][r][xp],
+                                                lds[s - 1][r - 1][lane], lds[s - 1][r + 1][lane], R[s - 1][0][m],
+                                                R[s - 1][2][m], R[s - 1][1][m], B[s][m]);
+                    }
+                } else if (s < NT) {
+                    // not needed; past the top wall this is the ghost plane nz
+#pragma unroll
+                    for (int m = 0; m < PTS; ++m) res[m] = R[s][0][m];
+                }
+                if (s < NT) {
+#pragma unroll
+                    for (int m = 0; m < PTS; ++m) {
+                        R[s][2][m] = R[s][1][m];
+                        R[s][1][m] = R[s][0][m];
+                        R[s][0][m] = res[m];
+                    }
+                    if (q == 0) {
+#pragma unroll
+                        for (int m = 0; m < PTS; ++m) R[s][1][m] = res[m];  // ghost plane -1
+                    }
+                } else if (q >= z0 && q < z1 && out_x) {
+                    const __amdgpu_buffer_rsrc_t ro = plane_rsrc(out + plane * q, pbytes);
+#pragma unroll
+                    for (int m = 0; m < PTS; ++m) {
+                        const int r = row[m];
+                        if (r >= NT && r < kTileY - NT && y0 + r < ny) buf_store(res[m], ro, col[m]);
+                    }
                 }
             }
+            __syncthreads();  // every read of this iteration's LDS planes is done
+#pragma unroll
+            for (int s = 0; s < NT; ++s)
+#pragma unroll
+                for (int m = 0; m < PTS; ++m) lds[s][row[m]][lane] = R[s][0][m];
+            __syncthreads();
         }
-        __syncthreads();  // every read of this iteration's LDS planes is done
-#pragma unroll
-        for (int s = 0; s < NT; ++s)
-#pragma unroll
-            for (int m = 0; m < PTS; ++m) lds[s][row[m]][lane] = R[s][0][m];
-        __syncthreads();
     }
 }
 
@@ -148,7 +277,7 @@ hipError_t launch_fused(const Geo& g, const T* b, const T* p, T* out, const Weig
     const int zchunk = (g.nz + nzc - 1) / nzc;
     nzc = (g.nz + zchunk - 1) / zchunk;
     hipLaunchKernelGGL((k_relax_fused<T, NT, WAVES>), dim3(tx, ty, nzc), dim3(64 * WAVES), 0, s, g.nx, g.ny, g.nz,
-                       zchunk, b, p, out, wts, (T)g.idx2, (T)g.idy2, (T)g.idz2);
+                       zchunk, b, p, out, stage_coefs(g, wts, NT));
     return hipGetLastError();
 }
 
@@ -156,9 +285,9 @@ hipError_t launch_fused(const Geo& g, const T* b, const T* p, T* out, const Weig
 // vertical neighbours in registers; used for grids narrower than a tile.
 template <typename T>
 __global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchunk, const T* __restrict__ b,
-                                               const T* __restrict__ p, T* __restrict__ out, T c, T idx2, T idy2,
-                                               T idz2)
+                                               const T* __restrict__ p, T* __restrict__ out, StageCoefs kc)
 {
+    const Coef<T> c{(T)kc.k0[0], (T)kc.kx[0], (T)kc.ky[0], (T)kc.kz[0], (T)kc.kb[0]};
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= nx || j >= ny) return;
@@ -172,9 +301,8 @@ __global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchun
     T pb = k0 > 0 ? p[o - plane + row + i] : pc;
     for (int k = k0; k < k1; ++k, o += plane) {
         const T pt = k + 1 < nz ? p[o + plane + row + i] : pc;
-        const T lap = (p[o + row + im] + p[o + row + ip] - T(2) * pc) * idx2 +
-                      (p[o + rowm + i] + p[o + rowp + i] - T(2) * pc) * idy2 + ((pt - pc) + (pb - pc)) * idz2;
-        out[o + row + i] = pc + c * (lap - b[o + row + i]);
+        out[o + row + i] =
+            sweep_point<T>(c, p[o + row + im], p[o + row + ip], p[o + rowm + i], p[o + rowp + i], pt, pb, pc, b[o + row + i]);
         pb = pc;
         pc = pt;
     }
@@ -182,7 +310,10 @@ __global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchun
 
 }  // namespace
 
-bool relax_fusable(const Geo& g) { return g.nx >= kTileX && g.ny >= kTileY; }
+bool relax_fusable(const Geo& g)
+{
+    return g.nx >= kTileX && g.ny >= kTileY && (long long)g.nx * g.ny < (1LL << 29);
+}
 
 template <typename T>
 hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, int nfused, hipStream_t s)
@@ -190,8 +321,8 @@ hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wt
     if (nfused == 1 || !relax_fusable(g)) {
         if (nfused != 1) return hipErrorInvalidValue;
         const March m = march_shape(g, 2048);
-        hipLaunchKernelGGL(k_relax<T>, m.grid, m.block, 0, s, g.nx, g.ny, g.nz, m.kchunk, b, p, out, (T)wts.c[0],
-                           (T)g.idx2, (T)g.idy2, (T)g.idz2);
+        hipLaunchKernelGGL(k_relax<T>, m.grid, m.block, 0, s, g.nx, g.ny, g.nz, m.kchunk, b, p, out,
+                           stage_coefs(g, wts, 1));
         return hipGetLastError();
     }
     if (nfused == 2) return launch_fused<T, 2, STP_RELAX_WAVES>(g, b, p, out, wts, s);
