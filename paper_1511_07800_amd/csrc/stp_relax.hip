@@ -16,13 +16,17 @@
 //
 // With HBM traffic cut by NT, the kernel is bound by vector-ALU issue and by
 // load latency along the march, which shape the code: the point update is
-// eight instructions, a stage skips (per wavefront) the rows and planes that
-// no later stage reads, the wall ghosts are stored in the rings instead of
-// selected per point, loads are addressed as a 32-bit lane offset on a
-// uniform plane base, and the next plane is requested one step ahead.
+// eight instructions with the walls folded into per-plane coefficients (no
+// ghost values, no selects per point); the march is unrolled so that ring
+// slots are static registers and nothing is copied between them; the next
+// plane is requested one step ahead; loads and stores are a 32-bit lane
+// offset on a uniform plane base; in FP32 a stage skips, per wavefront, the
+// rows no later stage reads.
 #include "stp_internal.h"
 
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 
 namespace stp {
 
@@ -35,18 +39,18 @@ static int kTargetBlocks = 2048;  // workgroups to aim for
 #ifndef STP_RELAX_WAVES
 #define STP_RELAX_WAVES 8      // wavefronts per workgroup; kTileY / waves rows per thread
 #endif
-#ifndef STP_RELAX_PF
-#define STP_RELAX_PF 1         // planes of p and b requested ahead of the one processed
-#endif
-constexpr int PF = STP_RELAX_PF;
 
 // Coefficients of one weighted Jacobi sweep, from omega and D = 2/dx^2 +
 // 2/dy^2 + 2/dz^2:  p + (omega/D)(L_p p - b)
 //   = (1 - omega) p + kx (pw + pe) + ky (ps + pn) + kz (pt + pb) - kb b,
 // kx = omega/(D dx^2), ky = omega/(D dy^2), kz = omega/(D dz^2), kb = omega/D:
 // the relaxation (1 - omega) p + omega J(p) of the plain Jacobi update J.
+// On a wall plane the zero-gradient ghost equals the centre value, so the
+// missing neighbour's kz moves onto the centre coefficient (k0w: one wall,
+// k0ww: both walls, nz = 1) and that neighbour gets coefficient 0.
 struct StageCoefs {
-    double k0[kMaxFused], kx[kMaxFused], ky[kMaxFused], kz[kMaxFused], kb[kMaxFused];
+    double k0[kMaxFused], k0w[kMaxFused], k0ww[kMaxFused], kx[kMaxFused], ky[kMaxFused], kz[kMaxFused],
+        kb[kMaxFused];
 };
 
 StageCoefs stage_coefs(const Geo& g, const Weights& w, int n)
@@ -55,19 +59,42 @@ StageCoefs stage_coefs(const Geo& g, const Weights& w, int n)
     StageCoefs k{};
     for (int s = 0; s < n; ++s) {
         const double kb = w.omega[s] / D;
-        k.k0[s] = 1.0 - w.omega[s];
         k.kx[s] = kb * g.idx2;
         k.ky[s] = kb * g.idy2;
         k.kz[s] = kb * g.idz2;
         k.kb[s] = kb;
+        k.k0[s] = 1.0 - w.omega[s];
+        k.k0w[s] = k.k0[s] + k.kz[s];
+        k.k0ww[s] = k.k0[s] + 2.0 * k.kz[s];
     }
     return k;
 }
 
 template <typename T>
 struct Coef {
-    T k0, kx, ky, kz, kb;
+    T k0, k0w, k0ww, kx, ky, kz, kb;
 };
+
+template <typename T>
+__device__ __forceinline__ Coef<T> coef_of(const StageCoefs& kc, int s)
+{
+    return Coef<T>{(T)kc.k0[s], (T)kc.k0w[s], (T)kc.k0ww[s], (T)kc.kx[s], (T)kc.ky[s], (T)kc.kz[s], (T)kc.kb[s]};
+}
+
+// the coefficients of plane q (uniform): centre, top and bottom neighbour
+template <typename T>
+struct PlaneCoef {
+    T k0, kzt, kzb;
+};
+template <typename T>
+__device__ __forceinline__ PlaneCoef<T> plane_coef(const Coef<T>& k, int q, int nz)
+{
+    // values, not references, in the selects: a select between two fields'
+    // addresses would keep the coefficients in memory
+    const T k0 = k.k0, k0w = k.k0w, k0ww = k.k0ww, kz = k.kz;
+    const bool top = q == nz - 1, bottom = q == 0;
+    return PlaneCoef<T>{top && bottom ? k0ww : (top || bottom ? k0w : k0), top ? T(0) : kz, bottom ? T(0) : kz};
+}
 
 template <typename T>
 __device__ __forceinline__ T fma_(T a, T b, T c);
@@ -76,17 +103,20 @@ __device__ __forceinline__ float fma_(float a, float b, float c) { return __buil
 template <>
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// One weighted Jacobi update of a cell from its six neighbours (zero-gradient
-// ghosts already substituted), with explicit fused multiply-adds in a fixed
-// order so the single-sweep and the fused kernels round identically: three
-// adds, one multiply, four fused multiply-adds.
+// One weighted Jacobi update of a cell from its six neighbours, with explicit
+// fused multiply-adds in a fixed order so the single-sweep and the fused
+// kernels round identically: two adds, one multiply, five fused
+// multiply-adds.  A wall neighbour has coefficient 0 (its value, any finite
+// number, drops out exactly).
 template <typename T>
-__device__ __forceinline__ T sweep_point(const Coef<T>& k, T pw, T pe, T ps, T pn, T pt, T pb, T pc, T bb)
+__device__ __forceinline__ T sweep_point(const Coef<T>& k, const PlaneCoef<T>& kq, T pw, T pe, T ps, T pn, T pt, T pb,
+                                         T pc, T bb)
 {
-    T acc = fma_(-k.kb, bb, k.k0 * pc);
+    T acc = fma_(-k.kb, bb, kq.k0 * pc);
     acc = fma_(k.kx, pw + pe, acc);
     acc = fma_(k.ky, ps + pn, acc);
-    return fma_(k.kz, pt + pb, acc);
+    acc = fma_(kq.kzt, pt, acc);
+    return fma_(kq.kzb, pb, acc);
 }
 
 // Buffer-resource access: a uniform plane base in scalar registers, a 32-bit
@@ -118,14 +148,30 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, un
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
 
+// f(t0 + U, U) for U = 0, 1, ..., in order, with U a compile-time constant
+template <typename F, int... U>
+__device__ __forceinline__ void unrolled(int t0, F& f, std::integer_sequence<int, U...>)
+{
+    (f(t0 + U, std::integral_constant<int, U>{}), ...);
+}
+
+// FP32: skip the rows a stage does not need (wave-uniform branches) and cap
+// the kernel at 128 VGPRs so two workgroups share a CU.  FP64: the rings
+// need about 200 VGPRs, one workgroup per CU, and straight-line code without
+// the row branches measured faster.
+template <typename T>
+constexpr bool kSkipRows = sizeof(T) == 4;
+template <typename T>
+constexpr int kMinWavesPerSimd = sizeof(T) == 4 ? 4 : 1;
+
 template <typename T, int NT, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_relax_fused(int nx, int ny, int nz, int zchunk,
+__global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused(int nx, int ny, int nz, int zchunk,
                                                             const T* __restrict__ b, const T* __restrict__ p,
                                                             T* __restrict__ out, StageCoefs kc)
 {
     constexpr int PTS = kTileY / WAVES;  // rows per thread
     constexpr int OX = kTileX - 2 * NT, OY = kTileY - 2 * NT;
-    __shared__ T lds[NT][kTileY][kTileX];
+    __shared__ T lds[NT][kTileY + 2][kTileX];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -152,116 +198,99 @@ __global__ __launch_bounds__(64 * WAVES) void k_relax_fused(int nx, int ny, int 
 
     Coef<T> c[NT];
 #pragma unroll
-    for (int s = 0; s < NT; ++s) c[s] = Coef<T>{(T)kc.k0[s], (T)kc.kx[s], (T)kc.ky[s], (T)kc.kz[s], (T)kc.kb[s]};
+    for (int s = 0; s < NT; ++s) c[s] = coef_of<T>(kc, s);
 
-    // rings: R[s][0] newest plane of stage s, R[s][1] the one before, R[s][2] before that
-    T R[NT][3][PTS];
-    T B[NT + 1][PTS];
+    // The march is unrolled by kUnroll = 6 steps so that every register slot
+    // is fixed at compile time and no value moves between registers: stage s
+    // keeps its last three planes in V[s][(q - t_begin) mod 3] and b of the
+    // last six planes sits in Bz[(q - t_begin) mod 6].  Plane t + 1 of p and
+    // b is requested while plane t is processed (p into Pn, b straight into
+    // its slot), so a step of loads is in flight across the barriers.  Loads
+    // past the top wall are clamped to plane nz - 1; ring slots of planes -1
+    // and nz hold finite stale values that the wall coefficients zero out.
+    constexpr int kUnroll = 6;
+    T V[NT][3][PTS];
+    T Bz[kUnroll][PTS];
+    T Pn[PTS];
 #pragma unroll
     for (int s = 0; s < NT; ++s)
 #pragma unroll
-        for (int m = 0; m < PTS; ++m) R[s][0][m] = R[s][1][m] = R[s][2][m] = T(0);
+        for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int s = 0; s <= NT; ++s)
+            for (int m = 0; m < PTS; ++m) V[s][k][m] = T(0);
 #pragma unroll
-        for (int m = 0; m < PTS; ++m) B[s][m] = T(0);
+    for (int k = 0; k < kUnroll; ++k)
+#pragma unroll
+        for (int m = 0; m < PTS; ++m) Bz[k][m] = T(0);
 
-    // Plane t + PF is requested while plane t is processed, into a register
-    // slot chosen statically (the loop is unrolled by PF), so PF planes of
-    // loads stay in flight across the barriers instead of one load latency
-    // being exposed per z step.  Planes past the top wall are clamped to
-    // nz - 1, which is the zero-gradient ghost plane of stage 0.
-    T Pq[PF][PTS], Bq[PF][PTS];
     const int t_begin = max(0, z0 - NT);
     const int t_end = z1 - 1 + NT;  // the final stage reaches plane z1 - 1
-#pragma unroll
-    for (int d = 0; d < PF; ++d) {
-        const long long o = plane * min(t_begin + d, nz - 1);
+    {
+        const long long o = plane * t_begin;
         const __amdgpu_buffer_rsrc_t rp = plane_rsrc(p + o, pbytes), rb = plane_rsrc(b + o, pbytes);
 #pragma unroll
         for (int m = 0; m < PTS; ++m) {
-            Pq[d][m] = buf_load<T>(rp, col[m]);
-            Bq[d][m] = buf_load<T>(rb, col[m]);
+            Pn[m] = buf_load<T>(rp, col[m]);
+            Bz[0][m] = buf_load<T>(rb, col[m]);
         }
     }
-    for (int tb = t_begin; tb <= t_end; tb += PF) {
-#pragma unroll
-        for (int d = 0; d < PF; ++d) {
-            const int t = tb + d;
-            if (t > t_end) break;
-            // stage 0: plane t from its slot, which then requests plane t + PF
-            const long long o = plane * min(t + PF, nz - 1);
+
+    // z step t at unroll position U = (t - t_begin) mod kUnroll
+    auto step = [&](const int t, auto U) {
+        constexpr int u = decltype(U)::value;
+        // slot of plane t - k in the stage rings and in the b ring
+        auto vs = [](int k) { return ((u - k) % 3 + 3) % 3; };
+        auto bs = [](int k) { return ((u - k) % kUnroll + kUnroll) % kUnroll; };
+        if (t > t_end) return;
+        // stage 0: plane t arrives; plane t + 1 is requested
+        {
+            const long long o = plane * min(t + 1, nz - 1);
             const __amdgpu_buffer_rsrc_t rp = plane_rsrc(p + o, pbytes), rb = plane_rsrc(b + o, pbytes);
 #pragma unroll
             for (int m = 0; m < PTS; ++m) {
-                R[0][2][m] = R[0][1][m];
-                R[0][1][m] = R[0][0][m];
-                R[0][0][m] = Pq[d][m];
-#pragma unroll
-                for (int s = NT; s > 0; --s) B[s][m] = B[s - 1][m];
-                B[0][m] = Bq[d][m];
-                Pq[d][m] = buf_load<T>(rp, col[m]);
-                Bq[d][m] = buf_load<T>(rb, col[m]);
+                V[0][vs(0)][m] = Pn[m];
+                Pn[m] = buf_load<T>(rp, col[m]);
+                Bz[bs(-1)][m] = buf_load<T>(rb, col[m]);
             }
-            // Zero-gradient walls: every ring holds, in place of plane -1 and
-            // plane nz, a copy of plane 0 and plane nz - 1 of its stage, so
-            // the point update needs no select.  Stage 0 gets plane nz - 1
-            // again from the clamped loads, plane -1 here.
-            if (t == 0) {
-#pragma unroll
-                for (int m = 0; m < PTS; ++m) R[0][1][m] = R[0][0][m];
-            }
-            // stages 1..NT: stage s produces plane q = t - s.  Stage s is
-            // needed only on rows [s, 32 - s) and planes [z0 - (NT - s),
-            // z1 + (NT - s)) inside the walls; both tests are uniform per
-            // wavefront, so skipped rows and planes cost no issue slots.
-#pragma unroll
-            for (int s = 1; s <= NT; ++s) {
-                const int q = t - s;
-                T res[PTS];
-                if (q >= max(0, z0 - (NT - s)) && q <= min(nz - 1, z1 - 1 + (NT - s))) {
-#pragma unroll
-                    for (int m = 0; m < PTS; ++m) {
-                        const int r = row[m];
-                        res[m] = R[s - 1][1][m];
-                        if (r < s || r >= kTileY - s) continue;
-                        res[m] = sweep_point<T>(c[s - 1], lds[s - 1][r][xm], lds[s - 1][r][xp],
-                                                lds[s - 1][r - 1][lane], lds[s - 1][r + 1][lane], R[s - 1][0][m],
-                                                R[s - 1][2][m], R[s - 1][1][m], B[s][m]);
-                    }
-                } else if (s < NT) {
-                    // not needed; past the top wall this is the ghost plane nz
-#pragma unroll
-                    for (int m = 0; m < PTS; ++m) res[m] = R[s][0][m];
-                }
-                if (s < NT) {
-#pragma unroll
-                    for (int m = 0; m < PTS; ++m) {
-                        R[s][2][m] = R[s][1][m];
-                        R[s][1][m] = R[s][0][m];
-                        R[s][0][m] = res[m];
-                    }
-                    if (q == 0) {
-#pragma unroll
-                        for (int m = 0; m < PTS; ++m) R[s][1][m] = res[m];  // ghost plane -1
-                    }
-                } else if (q >= z0 && q < z1 && out_x) {
-                    const __amdgpu_buffer_rsrc_t ro = plane_rsrc(out + plane * q, pbytes);
-#pragma unroll
-                    for (int m = 0; m < PTS; ++m) {
-                        const int r = row[m];
-                        if (r >= NT && r < kTileY - NT && y0 + r < ny) buf_store(res[m], ro, col[m]);
-                    }
-                }
-            }
-            __syncthreads();  // every read of this iteration's LDS planes is done
-#pragma unroll
-            for (int s = 0; s < NT; ++s)
-#pragma unroll
-                for (int m = 0; m < PTS; ++m) lds[s][row[m]][lane] = R[s][0][m];
-            __syncthreads();
         }
-    }
+        // stages 1..NT: stage s produces plane q = t - s from stage s-1's
+        // planes q + 1, q, q - 1.  Stage s is needed only on rows [s, 32 - s)
+        // and planes [z0 - (NT - s), z1 + (NT - s)) inside the walls; both
+        // tests are uniform per wavefront.  Rows outside that range (when not
+        // skipped) read the padding rows of LDS and are never used.
+#pragma unroll
+        for (int s = 1; s <= NT; ++s) {
+            const int q = t - s;
+            if (q < max(0, z0 - (NT - s)) || q > min(nz - 1, z1 - 1 + (NT - s))) continue;
+            const PlaneCoef<T> kq = plane_coef(c[s - 1], q, nz);
+            T res[PTS];
+#pragma unroll
+            for (int m = 0; m < PTS; ++m) {
+                if (kSkipRows<T> && (row[m] < s || row[m] >= kTileY - s)) continue;
+                const int r = row[m] + 1;  // LDS row (rows 0 and kTileY + 1 are padding)
+                res[m] = sweep_point<T>(c[s - 1], kq, lds[s - 1][r][xm], lds[s - 1][r][xp], lds[s - 1][r - 1][lane],
+                                        lds[s - 1][r + 1][lane], V[s - 1][vs(s - 1)][m], V[s - 1][vs(s + 1)][m],
+                                        V[s - 1][vs(s)][m], Bz[bs(s)][m]);
+                if (s < NT) V[s][vs(s)][m] = res[m];
+            }
+            if (s == NT && q >= z0 && out_x) {
+                const __amdgpu_buffer_rsrc_t ro = plane_rsrc(out + plane * q, pbytes);
+#pragma unroll
+                for (int m = 0; m < PTS; ++m) {
+                    const int r = row[m];
+                    if (r >= NT && r < kTileY - NT && y0 + r < ny) buf_store(res[m], ro, col[m]);
+                }
+            }
+        }
+        __syncthreads();  // every read of this step's LDS planes is done
+#pragma unroll
+        for (int s = 0; s < NT; ++s)
+#pragma unroll
+            for (int m = 0; m < PTS; ++m) lds[s][row[m] + 1][lane] = V[s][vs(s)][m];
+        __syncthreads();
+    };
+
+    for (int tb = t_begin; tb <= t_end; tb += kUnroll) unrolled(tb, step, std::make_integer_sequence<int, kUnroll>{});
 }
 
 template <typename T, int NT, int WAVES>
@@ -287,7 +316,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchunk, const T* __restrict__ b,
                                                const T* __restrict__ p, T* __restrict__ out, StageCoefs kc)
 {
-    const Coef<T> c{(T)kc.k0[0], (T)kc.kx[0], (T)kc.ky[0], (T)kc.kz[0], (T)kc.kb[0]};
+    const Coef<T> c = coef_of<T>(kc, 0);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= nx || j >= ny) return;
@@ -301,8 +330,8 @@ __global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchun
     T pb = k0 > 0 ? p[o - plane + row + i] : pc;
     for (int k = k0; k < k1; ++k, o += plane) {
         const T pt = k + 1 < nz ? p[o + plane + row + i] : pc;
-        out[o + row + i] =
-            sweep_point<T>(c, p[o + row + im], p[o + row + ip], p[o + rowm + i], p[o + rowp + i], pt, pb, pc, b[o + row + i]);
+        out[o + row + i] = sweep_point<T>(c, plane_coef(c, k, nz), p[o + row + im], p[o + row + ip], p[o + rowm + i],
+                                          p[o + rowp + i], pt, pb, pc, b[o + row + i]);
         pb = pc;
         pc = pt;
     }
