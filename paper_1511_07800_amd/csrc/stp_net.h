@@ -60,6 +60,8 @@ private:
     // parameters
     float *P_ = nullptr, *G_ = nullptr, *M_ = nullptr, *V_ = nullptr;
     uint16_t *Wb_ = nullptr, *Wt_ = nullptr;
+    uint16_t* Wf_ = nullptr;       // fragment-ordered weights of the forward kernels
+    long long wf_off_[kLayers] = {};
     // activations (channels-last BF16)
     uint16_t *X_ = nullptr, *C1_ = nullptr, *D1_ = nullptr, *Q1_ = nullptr, *C2_ = nullptr, *D2_ = nullptr,
              *Q2_ = nullptr, *E3_ = nullptr;

@@ -231,6 +231,227 @@ hipError_t conv(const Lvl& L, const uint16_t* in, const uint16_t* w, const float
     return hipGetLastError();
 }
 
+// ---- plane-marching convolution (forward) ----------------------------------------
+//
+// The same operator as k_conv for one 16-channel output tile per workgroup,
+// computed as D^T = W X^T with v_mfma_f32_16x16x32_bf16 (A: 16 output channels
+// x 32 of K, B: 32 of K x 16 cells).  Within one dz slice K is ordered
+// (dy, dx, ci): K9 = 9 CIN, padded to whole 32-chunks with zero weights.  The
+// workgroup owns a 32 x (2 WAVES) tile of an x-y plane and marches along z one
+// INPUT plane at a time: the plane, with a one-cell halo (periodic in x and y),
+// sits in LDS, and every B fragment read from it feeds the three dz weight
+// slices, accumulating into output planes j + 1, j and j - 1; plane j - 1 is
+// then complete and stored.  Input fragments are thus read from LDS once per
+// plane instead of 27 times from cache, the weights of the tile sit in LDS in
+// fragment order (one 16-byte read per lane), and the next input plane is
+// loaded into registers while the current one is computed.  The input may be
+// the concatenation of two tensors, the first optionally at half resolution
+// (nearest upsampling folded into the load).
+
+struct SrcView {  // channels-last BF16 slice: element (cell, c) at p[cell * stride + off + c]
+    const uint16_t* p;
+    int stride, off;
+    int nx, ny, nz;  // its own grid (the coarse grid when upsampled)
+};
+
+template <int CIN, int WAVES>
+struct PlaneTile {
+    static constexpr int TX = 32, TY = 2 * WAVES, HX = TX + 2, HY = TY + 2;
+    static constexpr int CU = CIN / 8;  // 16-byte channel groups per cell
+    // LDS bytes per cell: an odd number of 16-byte units, so the 16 cells of a
+    // fragment fall on distinct banks
+    static constexpr int CSTR = (CU % 2 == 1 ? CU : CU + 1) * 16;
+    static constexpr int PLANE = HX * HY * CSTR;
+    static constexpr int KC = (9 * CIN + 31) / 32;  // K chunks per dz slice
+    static constexpr int WBYTES = 3 * KC * 64 * 16;  // fragment-ordered weights of one output tile
+    static constexpr int NCHUNK = HX * HY * CU;      // 16-byte loads per plane
+    static constexpr int PER_THREAD = (NCHUNK + 64 * WAVES - 1) / (64 * WAVES);
+};
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+template <int CIN, int CA, bool UPA, int WAVES, int MODE>
+__global__ __launch_bounds__(64 * WAVES) void k_conv_march(Lvl L, SrcView A, SrcView B, const u32x4* __restrict__ wf,
+                                                           const float* __restrict__ bias, void* __restrict__ out,
+                                                           int ostride, int ooff, int relu, int zchunk, int ncot)
+{
+    using PT = PlaneTile<CIN, WAVES>;
+    static_assert(CIN % 8 == 0 && CA % 8 == 0 && CA <= CIN, "channel groups of 8");
+    __shared__ __align__(16) unsigned char sx[PT::PLANE];
+    __shared__ u32x4 sw[PT::WBYTES / 16];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int jc = lane & 15, g = lane >> 4;
+    const int cot = blockIdx.z % ncot;
+    const int z0 = (blockIdx.z / ncot) * zchunk, z1 = min(L.nz, z0 + zchunk);
+    const int x0 = blockIdx.x * PT::TX, y0 = blockIdx.y * PT::TY;
+
+    for (int e = tid; e < PT::WBYTES / 16; e += 64 * WAVES) sw[e] = wf[(long long)cot * (PT::WBYTES / 16) + e];
+
+    // this thread's 16-byte slots of the halo plane: source, offset within a
+    // source plane, LDS offset
+    const long long planeA = (long long)A.nx * A.ny * A.stride, planeB = (long long)B.nx * B.ny * B.stride;
+    int soff[PT::PER_THREAD], loff[PT::PER_THREAD];
+    bool fromA[PT::PER_THREAD];
+#pragma unroll
+    for (int s = 0; s < PT::PER_THREAD; ++s) {
+        const int e = min(tid + s * 64 * WAVES, PT::NCHUNK - 1);
+        const int h = e / PT::CU, cu = e - h * PT::CU;
+        const int hx = h % PT::HX, hy = h / PT::HX;
+        int gx = (x0 - 1 + hx) % L.nx, gy = (y0 - 1 + hy) % L.ny;
+        gx = gx < 0 ? gx + L.nx : gx;
+        gy = gy < 0 ? gy + L.ny : gy;
+        const int c = 8 * cu;
+        fromA[s] = c < CA;
+        if (c < CA) {
+            const int ax = UPA ? gx / 2 : gx, ay = UPA ? gy / 2 : gy;
+            soff[s] = (ay * A.nx + ax) * A.stride + A.off + c;
+        } else {
+            soff[s] = (gy * B.nx + gx) * B.stride + B.off + (c - CA);
+        }
+        loff[s] = h * PT::CSTR + 16 * cu;
+    }
+    u32x4 pre[PT::PER_THREAD];
+    auto load_plane = [&](int j) {
+#pragma unroll
+        for (int s = 0; s < PT::PER_THREAD; ++s) {
+            const uint16_t* src = fromA[s] ? A.p + (long long)(UPA ? j / 2 : j) * planeA + soff[s]
+                                           : B.p + (long long)j * planeB + soff[s];
+            pre[s] = *reinterpret_cast<const u32x4*>(src);
+        }
+    };
+    auto store_plane = [&]() {
+#pragma unroll
+        for (int s = 0; s < PT::PER_THREAD; ++s)
+            if (tid + s * 64 * WAVES < PT::NCHUNK) *reinterpret_cast<u32x4*>(sx + loff[s]) = pre[s];
+    };
+
+    // K offsets of this lane's B fragments: chunk q, group g covers k = 32 q + 8 g
+    // .. + 7, i.e. tap9 = k / CIN (dy + 1 = tap9 / 3, dx + 1 = tap9 % 3), channels c
+    int koff[PT::KC];
+#pragma unroll
+    for (int q = 0; q < PT::KC; ++q) {
+        const int k = 32 * q + 8 * g;
+        const int tap = k / CIN, c = k - tap * CIN;
+        koff[q] = k < 9 * CIN ? ((tap / 3) * PT::HX + tap % 3) * PT::CSTR + 2 * c : -1;
+    }
+    // this wave's four 16-cell tiles: rows 2 wave + (n >> 1), x halves n & 1
+    int cbase[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) cbase[n] = ((2 * wave + (n >> 1)) * PT::HX + 16 * (n & 1) + jc) * PT::CSTR;
+
+    float bv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bv[r] = bias ? bias[16 * cot + 4 * g + r] : 0.f;
+
+    // acc[0]: output plane j + 1 (dz = -1), acc[1]: plane j, acc[2]: plane j - 1
+    floatx4 acc[3][4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[d][n] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    auto store_out = [&](int z) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int x = x0 + 16 * (n & 1) + jc, y = y0 + 2 * wave + (n >> 1);
+            if (x >= L.nx || y >= L.ny) continue;
+            const long long v = ((long long)z * L.ny + y) * L.nx + x;
+            if (MODE == OUT_BF16) {
+                unsigned h[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float val = acc[2][n][r] + bv[r];
+                    if (relu) val = fmaxf(val, 0.f);
+                    h[r] = f2bf(val);
+                }
+                *reinterpret_cast<u32x2*>(static_cast<uint16_t*>(out) + v * ostride + ooff + 16 * cot + 4 * g) =
+                    u32x2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+            } else if (g == 0) {  // OUT_HEAD: channel 0 only
+                static_cast<float*>(out)[v] = acc[2][n][0] + bv[0];
+            }
+        }
+    };
+
+    __syncthreads();  // weights in LDS
+    int j = z0 - 1;
+    if (j >= 0) {
+        load_plane(j);
+        store_plane();
+    }
+    __syncthreads();
+    for (; j <= z1; ++j) {
+        const bool next = j + 1 <= z1 && j + 1 < L.nz;  // uniform
+        if (next) load_plane(j + 1);
+        if (j >= 0 && j < L.nz) {
+#pragma unroll
+            for (int q = 0; q < PT::KC; ++q) {
+                bf16x8 bx[4];
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    u32x4 raw = u32x4{0u, 0u, 0u, 0u};
+                    if (koff[q] >= 0) raw = *reinterpret_cast<const u32x4*>(sx + cbase[n] + koff[q]);
+                    bx[n] = __builtin_bit_cast(bf16x8, raw);
+                }
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const bf16x8 aw = __builtin_bit_cast(bf16x8, sw[(d * PT::KC + q) * 64 + lane]);
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) acc[d][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[n], acc[d][n], 0, 0, 0);
+                }
+            }
+        }
+        if (j - 1 >= z0) store_out(j - 1);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            acc[2][n] = acc[1][n];
+            acc[1][n] = acc[0][n];
+            acc[0][n] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        __syncthreads();  // all reads of plane j done
+        if (next) store_plane();
+        __syncthreads();
+    }
+}
+
+template <int CIN, int CA, bool UPA, int WAVES, int MODE>
+hipError_t conv_march(const Lvl& L, const SrcView& A, const SrcView& B, const uint16_t* wf, int ncot,
+                      const float* bias, void* out, int ostride, int ooff, int relu, hipStream_t s)
+{
+    using PT = PlaneTile<CIN, WAVES>;
+    const int tx = (L.nx + PT::TX - 1) / PT::TX, ty = (L.ny + PT::TY - 1) / PT::TY;
+    // z chunks: about 2048 workgroups, at least 8 output planes each
+    const long long tiles = (long long)tx * ty * ncot;
+    int nzc = (int)std::max<long long>(1, std::min<long long>(L.nz / 8, (2048 + tiles - 1) / tiles));
+    const int zchunk = (L.nz + nzc - 1) / nzc;
+    nzc = (L.nz + zchunk - 1) / zchunk;
+    hipLaunchKernelGGL((k_conv_march<CIN, CA, UPA, WAVES, MODE>), dim3(tx, ty, nzc * ncot), dim3(64 * WAVES), 0, s, L, A,
+                       B, reinterpret_cast<const u32x4*>(wf), bias, out, ostride, ooff, relu, zchunk, ncot);
+    return hipGetLastError();
+}
+
+// Wf[cot][dz][q][lane][e] = Wb[dz 9 + tap9][16 cot + (lane & 15)][c + e] with
+// k = 32 q + 8 (lane >> 4) + e, tap9 = k / cin_eff, c = k % cin_eff (zero for
+// k >= 9 cin_eff): the A fragments of k_conv_march in reading order.
+__global__ void k_pack_frag(const uint16_t* __restrict__ Wb, int cout, int cin_mem, int cin_eff, int kc,
+                            uint16_t* __restrict__ Wf)
+{
+    const long long total = (long long)(cout / 16) * 3 * kc * 64 * 8;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+        const int el = (int)(e % 8), lane = (int)((e / 8) % 64), q = (int)((e / 512) % kc);
+        const int dz = (int)((e / (512LL * kc)) % 3), cot = (int)(e / (1536LL * kc));
+        const int k = 32 * q + 8 * (lane >> 4) + el;
+        uint16_t h = 0;
+        if (k < 9 * cin_eff) {
+            const int tap = k / cin_eff, c = k % cin_eff;
+            h = Wb[((long long)(dz * 9 + tap) * cout + 16 * cot + (lane & 15)) * cin_mem + c];
+        }
+        Wf[e] = h;
+    }
+}
+
 // ---- weight gradient ----------------------------------------------------------------
 
 // part[chunk][tap][co][ci] = sum over the chunk's cells v of
@@ -549,7 +770,7 @@ bool NetModel::grid_ok(int nx, int ny, int nz)
 
 namespace {
 struct Sizes {
-    long long v1, v2, v4, nparam, nwb;
+    long long v1, v2, v4, nparam, nwb, nwf;
     size_t off[40];
     size_t total;
 };
@@ -559,6 +780,11 @@ const int kCout[6] = {16, 32, 64, 32, 16, 16};
 const int kCinL[6] = {2, 16, 32, 96, 48, 16};
 const int kCoutL[6] = {16, 32, 64, 32, 16, 1};
 const int kLevel[6] = {0, 1, 2, 1, 0, 0};
+// input channels the plane-marching kernel reads (the first layer's two
+// logical channels sit in a group of 8)
+const int kCinEff[6] = {8, 16, 32, 96, 48, 16};
+int frag_chunks(int l) { return (9 * kCinEff[l] + 31) / 32; }
+long long frag_elems(int l) { return (long long)(kCout[l] / 16) * 3 * frag_chunks(l) * 64 * 8; }
 constexpr long long kWpartFloats = 16LL * 1024 * 1024;  // weight-gradient partial sums (64 MiB)
 
 Sizes sizes(int nx, int ny, int nz, bool training)
@@ -569,9 +795,11 @@ Sizes sizes(int nx, int ny, int nz, bool training)
     S.v4 = S.v1 / 64;
     S.nparam = 0;
     S.nwb = 0;
+    S.nwf = 0;
     for (int l = 0; l < 6; ++l) {
         S.nparam += 27LL * kCin[l] * kCout[l] + kCout[l];
         S.nwb += 27LL * kCin[l] * kCout[l];
+        S.nwf += frag_elems(l);
     }
     size_t o = 0;
     int k = 0;
@@ -596,19 +824,20 @@ Sizes sizes(int nx, int ny, int nz, bool training)
     take(S.v1 * 4);      // 14 Y
     take(2 * kRedBlocks * 8);  // 15 reduction partials
     take(64 * 8);        // 16 scalars
+    take(S.nwf * 2);     // 17 fragment-ordered BF16 weights
     if (training) {
-        take(S.v1 * 16 * 2);  // 17 gY
-        take(S.v1 * 16 * 4);  // 18 dD1
-        take(S.v1 * 16 * 2);  // 19 gD1
-        take(S.v1 * 48 * 4);  // 20 dC1
-        take(S.v2 * 32 * 2);  // 21 gD2
-        take(S.v2 * 96 * 4);  // 22 dC2
-        take(S.v4 * 64 * 2);  // 23 gE3
-        take(S.v4 * 32 * 4);  // 24 dQ2
-        take(S.v2 * 32 * 2);  // 25 gE2
-        take(S.v2 * 16 * 4);  // 26 dQ1
-        take(S.v1 * 16 * 2);  // 27 gE1
-        take(kWpartFloats * 4);  // 28 weight partials
+        take(S.v1 * 16 * 2);  // 18 gY
+        take(S.v1 * 16 * 4);  // 19 dD1
+        take(S.v1 * 16 * 2);  // 20 gD1
+        take(S.v1 * 48 * 4);  // 21 dC1
+        take(S.v2 * 32 * 2);  // 22 gD2
+        take(S.v2 * 96 * 4);  // 23 dC2
+        take(S.v4 * 64 * 2);  // 24 gE3
+        take(S.v4 * 32 * 4);  // 25 dQ2
+        take(S.v2 * 32 * 2);  // 26 gE2
+        take(S.v2 * 16 * 4);  // 27 dQ1
+        take(S.v1 * 16 * 2);  // 28 gE1
+        take(kWpartFloats * 4);  // 29 weight partials
     }
     S.total = o;
     return S;
@@ -666,19 +895,27 @@ NetModel::NetModel(int nx, int ny, int nz, double idx2, double idy2, double idz2
     Y_ = (float*)(b + S.off[14]);
     red_ = (double*)(b + S.off[15]);
     sc_ = (double*)(b + S.off[16]);
+    Wf_ = (uint16_t*)(b + S.off[17]);
+    {
+        long long fo = 0;
+        for (int l = 0; l < kLayers; ++l) {
+            wf_off_[l] = fo;
+            fo += frag_elems(l);
+        }
+    }
     if (training) {
-        gY_ = (uint16_t*)(b + S.off[17]);
-        dD1_ = (float*)(b + S.off[18]);
-        gD1_ = (uint16_t*)(b + S.off[19]);
-        dC1_ = (float*)(b + S.off[20]);
-        gD2_ = (uint16_t*)(b + S.off[21]);
-        dC2_ = (float*)(b + S.off[22]);
-        gE3_ = (uint16_t*)(b + S.off[23]);
-        dQ2_ = (float*)(b + S.off[24]);
-        gE2_ = (uint16_t*)(b + S.off[25]);
-        dQ1_ = (float*)(b + S.off[26]);
-        gE1_ = (uint16_t*)(b + S.off[27]);
-        wpart_ = (float*)(b + S.off[28]);
+        gY_ = (uint16_t*)(b + S.off[18]);
+        dD1_ = (float*)(b + S.off[19]);
+        gD1_ = (uint16_t*)(b + S.off[20]);
+        dC1_ = (float*)(b + S.off[21]);
+        gD2_ = (uint16_t*)(b + S.off[22]);
+        dC2_ = (float*)(b + S.off[23]);
+        gE3_ = (uint16_t*)(b + S.off[24]);
+        dQ2_ = (float*)(b + S.off[25]);
+        gE2_ = (uint16_t*)(b + S.off[26]);
+        dQ1_ = (float*)(b + S.off[27]);
+        gE1_ = (uint16_t*)(b + S.off[28]);
+        wpart_ = (float*)(b + S.off[29]);
         wpart_floats_ = kWpartFloats;
     }
 }
@@ -705,6 +942,10 @@ hipError_t NetModel::convert_weights()
         hipLaunchKernelGGL(k_convert, dim3(g1(27LL * ly.cin * ly.cout)), dim3(256), 0, s_, P_ + ly.w_off, ly.cout, ly.cin,
                            Wb_ + ly.wb_off, Wt_ + ly.wb_off);
         hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_pack_frag, dim3(g1(frag_elems(l))), dim3(256), 0, s_, Wb_ + ly.wb_off, ly.cout, ly.cin,
+                           kCinEff[l], frag_chunks(l), Wf_ + wf_off_[l]);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -744,26 +985,41 @@ hipError_t NetModel::forward()
 {
     const Lvl l0{nx_[0], ny_[0], nz_[0], nv_[0]}, l1{nx_[1], ny_[1], nz_[1], nv_[1]}, l2{nx_[2], ny_[2], nz_[2], nv_[2]};
     const float* P = P_;
+    auto view = [&](const uint16_t* p, int stride, int off, int lvl) {
+        return SrcView{p, stride, off, nx_[lvl], ny_[lvl], nz_[lvl]};
+    };
+    const SrcView none{};
     // e1 = relu(conv1(x)) into channels 32..47 of C1
-    NCHK((conv<16, 16, OUT_BF16>(l0, X_, Wb_ + L_[0].wb_off, P + L_[0].b_off, C1_, 48, 32, 1, s_)));
+    NCHK((conv_march<8, 8, false, 8, OUT_BF16>(l0, view(X_, 16, 0, 0), none, Wf_ + wf_off_[0], 1, P + L_[0].b_off,
+                                                 C1_, 48, 32, 1, s_)));
     hipLaunchKernelGGL(k_pool, dim3(g1(l1.n * 16)), dim3(256), 0, s_, l1, C1_, 48, 32, 16, Q1_);
     NCHK(hipGetLastError());
     // e2 = relu(conv2(pool e1)) into channels 64..95 of C2
-    NCHK((conv<16, 32, OUT_BF16>(l1, Q1_, Wb_ + L_[1].wb_off, P + L_[1].b_off, C2_, 96, 64, 1, s_)));
+    NCHK((conv_march<16, 16, false, 8, OUT_BF16>(l1, view(Q1_, 16, 0, 1), none, Wf_ + wf_off_[1], 2, P + L_[1].b_off,
+                                                   C2_, 96, 64, 1, s_)));
     hipLaunchKernelGGL(k_pool, dim3(g1(l2.n * 32)), dim3(256), 0, s_, l2, C2_, 96, 64, 32, Q2_);
     NCHK(hipGetLastError());
     // e3 = relu(conv3(pool e2))
-    NCHK((conv<32, 64, OUT_BF16>(l2, Q2_, Wb_ + L_[2].wb_off, P + L_[2].b_off, E3_, 64, 0, 1, s_)));
-    // d2 = relu(conv4([up e3, e2]))
-    hipLaunchKernelGGL(k_up, dim3(g1(l1.n * 64)), dim3(256), 0, s_, l1, E3_, 64, C2_, 96, 0);
-    NCHK(hipGetLastError());
-    NCHK((conv<96, 32, OUT_BF16>(l1, C2_, Wb_ + L_[3].wb_off, P + L_[3].b_off, D2_, 32, 0, 1, s_)));
+    NCHK((conv_march<32, 32, false, 8, OUT_BF16>(l2, view(Q2_, 32, 0, 2), none, Wf_ + wf_off_[2], 4, P + L_[2].b_off,
+                                                   E3_, 64, 0, 1, s_)));
+    // d2 = relu(conv4([up e3, e2])); the upsampling is read directly from e3.
+    // Training keeps the concatenated tensor for the weight gradient.
+    if (training_) {
+        hipLaunchKernelGGL(k_up, dim3(g1(l1.n * 64)), dim3(256), 0, s_, l1, E3_, 64, C2_, 96, 0);
+        NCHK(hipGetLastError());
+    }
+    NCHK((conv_march<96, 64, true, 4, OUT_BF16>(l1, view(E3_, 64, 0, 2), view(C2_, 96, 64, 1), Wf_ + wf_off_[3], 2,
+                                                  P + L_[3].b_off, D2_, 32, 0, 1, s_)));
     // d1 = relu(conv5([up d2, e1]))
-    hipLaunchKernelGGL(k_up, dim3(g1(l0.n * 32)), dim3(256), 0, s_, l0, D2_, 32, C1_, 48, 0);
-    NCHK(hipGetLastError());
-    NCHK((conv<48, 16, OUT_BF16>(l0, C1_, Wb_ + L_[4].wb_off, P + L_[4].b_off, D1_, 16, 0, 1, s_)));
+    if (training_) {
+        hipLaunchKernelGGL(k_up, dim3(g1(l0.n * 32)), dim3(256), 0, s_, l0, D2_, 32, C1_, 48, 0);
+        NCHK(hipGetLastError());
+    }
+    NCHK((conv_march<48, 32, true, 8, OUT_BF16>(l0, view(D2_, 32, 0, 1), view(C1_, 48, 32, 0), Wf_ + wf_off_[4], 1,
+                                                  P + L_[4].b_off, D1_, 16, 0, 1, s_)));
     // y = conv6(d1)
-    NCHK((conv<16, 16, OUT_HEAD>(l0, D1_, Wb_ + L_[5].wb_off, P + L_[5].b_off, Y_, 1, 0, 0, s_)));
+    NCHK((conv_march<16, 16, false, 8, OUT_HEAD>(l0, view(D1_, 16, 0, 0), none, Wf_ + wf_off_[5], 1, P + L_[5].b_off,
+                                                   Y_, 1, 0, 0, s_)));
     return hipSuccess;
 }
 
