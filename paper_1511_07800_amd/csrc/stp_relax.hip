@@ -36,6 +36,7 @@ constexpr int kTileX = 64;  // one wavefront across x
 constexpr int kTileY = 32;
 static int kMinChunk = 48;       // planes per z-chunk, at least (measured best at 512x256x192)
 static int kTargetBlocks = 2048;  // workgroups to aim for
+constexpr int kXcds = 8;          // accelerator complex dies of an MI355X, each with its own L2
 #ifndef STP_RELAX_WAVES
 #define STP_RELAX_WAVES 8      // wavefronts per workgroup; kTileY / waves rows per thread
 #endif
@@ -166,18 +167,27 @@ constexpr int kMinWavesPerSimd = sizeof(T) == 4 ? 4 : 1;
 
 template <typename T, int NT, int WAVES>
 __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused(int nx, int ny, int nz, int zchunk,
+                                                            int tx, int ty, int ntiles,
                                                             const T* __restrict__ b, const T* __restrict__ p,
                                                             T* __restrict__ out, StageCoefs kc)
 {
+    // Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD
+    // w mod 8).  Tile L = (w mod 8) * (grid / 8) + w / 8 gives every XCD a
+    // contiguous run of tiles (x fastest, then y, then z-chunk), so the halo
+    // a tile shares with its neighbours is read through the same L2.
+    const int per_xcd = gridDim.x / kXcds;
+    const int tile = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+    if (tile >= ntiles) return;
+    const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
     constexpr int PTS = kTileY / WAVES;  // rows per thread
     constexpr int OX = kTileX - 2 * NT, OY = kTileY - 2 * NT;
     __shared__ T lds[NT][kTileY + 2][kTileX];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int x0 = blockIdx.x * OX - NT;  // tile origin (may be negative: wrapped)
-    const int y0 = blockIdx.y * OY - NT;
-    const int z0 = blockIdx.z * zchunk, z1 = min(nz, z0 + zchunk);
+    const int x0 = bx * OX - NT;  // tile origin (may be negative: wrapped)
+    const int y0 = by * OY - NT;
+    const int z0 = bz * zchunk, z1 = min(nz, z0 + zchunk);
     const long long plane = (long long)nx * ny;
     const unsigned pbytes = (unsigned)(plane * (long long)sizeof(T));
 
@@ -305,8 +315,10 @@ hipError_t launch_fused(const Geo& g, const T* b, const T* p, T* out, const Weig
         1, std::min<long long>(g.nz / kMinChunk, (kTargetBlocks + tiles - 1) / tiles));
     const int zchunk = (g.nz + nzc - 1) / nzc;
     nzc = (g.nz + zchunk - 1) / zchunk;
-    hipLaunchKernelGGL((k_relax_fused<T, NT, WAVES>), dim3(tx, ty, nzc), dim3(64 * WAVES), 0, s, g.nx, g.ny, g.nz,
-                       zchunk, b, p, out, stage_coefs(g, wts, NT));
+    const int ntiles = tx * ty * nzc;
+    const int grid = (ntiles + kXcds - 1) / kXcds * kXcds;  // whole rounds over the XCDs
+    hipLaunchKernelGGL((k_relax_fused<T, NT, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, g.nx, g.ny, g.nz, zchunk,
+                       tx, ty, ntiles, b, p, out, stage_coefs(g, wts, NT));
     return hipGetLastError();
 }
 
