@@ -33,9 +33,9 @@ namespace stp {
 namespace {
 
 constexpr int kTileX = 64;  // one wavefront across x
-constexpr int kTileY = 32;
-static int kMinChunk = 48;       // planes per z-chunk, at least (measured best at 512x256x192)
-static int kTargetBlocks = 2048;  // workgroups to aim for
+constexpr int kTileY = 32;  // rows updated by a workgroup; two more halo rows are only loaded
+constexpr int kRows = kTileY + 2;
+static int kMinChunk = 8;  // planes per z-chunk, at least
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X, each with its own L2
 #ifndef STP_RELAX_WAVES
 #define STP_RELAX_WAVES 8      // wavefronts per workgroup; kTileY / waves rows per thread
@@ -49,24 +49,27 @@ constexpr int kXcds = 8;          // accelerator complex dies of an MI355X, each
 // On a wall plane the zero-gradient ghost equals the centre value, so the
 // missing neighbour's kz moves onto the centre coefficient (k0w: one wall,
 // k0ww: both walls, nz = 1) and that neighbour gets coefficient 0.
+// Computed in double on the host and rounded once to the kernel's type, so
+// the kernel holds them in scalar registers as they arrive.
+template <typename T>
 struct StageCoefs {
-    double k0[kMaxFused], k0w[kMaxFused], k0ww[kMaxFused], kx[kMaxFused], ky[kMaxFused], kz[kMaxFused],
-        kb[kMaxFused];
+    T k0[kMaxFused], k0w[kMaxFused], k0ww[kMaxFused], kx[kMaxFused], ky[kMaxFused], kz[kMaxFused], kb[kMaxFused];
 };
 
-StageCoefs stage_coefs(const Geo& g, const Weights& w, int n)
+template <typename T>
+StageCoefs<T> stage_coefs(const Geo& g, const Weights& w, int n)
 {
     const double D = 2.0 * (g.idx2 + g.idy2 + g.idz2);
-    StageCoefs k{};
+    StageCoefs<T> k{};
     for (int s = 0; s < n; ++s) {
-        const double kb = w.omega[s] / D;
-        k.kx[s] = kb * g.idx2;
-        k.ky[s] = kb * g.idy2;
-        k.kz[s] = kb * g.idz2;
-        k.kb[s] = kb;
-        k.k0[s] = 1.0 - w.omega[s];
-        k.k0w[s] = k.k0[s] + k.kz[s];
-        k.k0ww[s] = k.k0[s] + 2.0 * k.kz[s];
+        const double kb = w.omega[s] / D, kz = kb * g.idz2, k0 = 1.0 - w.omega[s];
+        k.kx[s] = (T)(kb * g.idx2);
+        k.ky[s] = (T)(kb * g.idy2);
+        k.kz[s] = (T)kz;
+        k.kb[s] = (T)kb;
+        k.k0[s] = (T)k0;
+        k.k0w[s] = (T)(k0 + kz);
+        k.k0ww[s] = (T)(k0 + 2.0 * kz);
     }
     return k;
 }
@@ -77,9 +80,9 @@ struct Coef {
 };
 
 template <typename T>
-__device__ __forceinline__ Coef<T> coef_of(const StageCoefs& kc, int s)
+__device__ __forceinline__ Coef<T> coef_of(const StageCoefs<T>& kc, int s)
 {
-    return Coef<T>{(T)kc.k0[s], (T)kc.k0w[s], (T)kc.k0ww[s], (T)kc.kx[s], (T)kc.ky[s], (T)kc.kz[s], (T)kc.kb[s]};
+    return Coef<T>{kc.k0[s], kc.k0w[s], kc.k0ww[s], kc.kx[s], kc.ky[s], kc.kz[s], kc.kb[s]};
 }
 
 // the coefficients of plane q (uniform): centre, top and bottom neighbour
@@ -169,7 +172,7 @@ template <typename T, int NT, int WAVES>
 __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused(int nx, int ny, int nz, int zchunk,
                                                             int tx, int ty, int ntiles,
                                                             const T* __restrict__ b, const T* __restrict__ p,
-                                                            T* __restrict__ out, StageCoefs kc)
+                                                            T* __restrict__ out, StageCoefs<T> kc)
 {
     // Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD
     // w mod 8).  Tile L = (w mod 8) * (grid / 8) + w / 8 gives every XCD a
@@ -180,8 +183,8 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
     if (tile >= ntiles) return;
     const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
     constexpr int PTS = kTileY / WAVES;  // rows per thread
-    constexpr int OX = kTileX - 2 * NT, OY = kTileY - 2 * NT;
-    __shared__ T lds[NT][kTileY + 2][kTileX];
+    constexpr int OX = kTileX - 2 * NT, OY = kRows - 2 * NT;
+    __shared__ T lds[NT][kRows][kTileX];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -195,14 +198,19 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
     const int gx = ((x0 + lane) % nx + nx) % nx;
     // byte offset of this thread's column within a plane: a 32-bit vector
     // offset on a uniform plane address (planes below 4 GiB)
+    // Tile rows 1..kTileY are updated (row[m] = 1 + wave + WAVES m); rows 0
+    // and kRows - 1 are the y halo of the first stage, loaded by the first
+    // and the last wavefront and never updated.
     unsigned col[PTS];
     int row[PTS];
 #pragma unroll
     for (int m = 0; m < PTS; ++m) {
-        row[m] = wave + WAVES * m;
+        row[m] = 1 + wave + WAVES * m;
         const int gy = ((y0 + row[m]) % ny + ny) % ny;
         col[m] = (unsigned)(gy * nx + gx) * (unsigned)sizeof(T);
     }
+    const int hrow = wave == 0 ? 0 : (wave == WAVES - 1 ? kRows - 1 : -1);  // uniform per wavefront
+    const unsigned hcol = (unsigned)(((((y0 + max(hrow, 0)) % ny + ny) % ny) * nx + gx)) * (unsigned)sizeof(T);
     const int xm = max(lane - 1, 0), xp = min(lane + 1, kTileX - 1);
     const bool out_x = lane >= NT && lane < kTileX - NT && x0 + lane < nx;
 
@@ -244,6 +252,10 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
             Bz[0][m] = buf_load<T>(rb, col[m]);
         }
     }
+    // halo row of the first stage: plane t + 1 is requested (Ph) when plane
+    // t arrives (Vh), and Vh goes to LDS at the end of step t
+    T Ph = T(0), Vh = T(0);
+    if (hrow >= 0) Ph = buf_load<T>(plane_rsrc(p + plane * t_begin, pbytes), hcol);
 
     // z step t at unroll position U = (t - t_begin) mod kUnroll
     auto step = [&](const int t, auto U) {
@@ -252,10 +264,15 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
         auto vs = [](int k) { return ((u - k) % 3 + 3) % 3; };
         auto bs = [](int k) { return ((u - k) % kUnroll + kUnroll) % kUnroll; };
         if (t > t_end) return;
-        // stage 0: plane t arrives; plane t + 1 is requested
+        // stage 0: plane t arrives; plane t + 1 is requested (the halo row's
+        // first: loads complete in order)
         {
             const long long o = plane * min(t + 1, nz - 1);
             const __amdgpu_buffer_rsrc_t rp = plane_rsrc(p + o, pbytes), rb = plane_rsrc(b + o, pbytes);
+            if (hrow >= 0) {
+                Vh = Ph;
+                Ph = buf_load<T>(rp, hcol);
+            }
 #pragma unroll
             for (int m = 0; m < PTS; ++m) {
                 V[0][vs(0)][m] = Pn[m];
@@ -276,8 +293,8 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
             T res[PTS];
 #pragma unroll
             for (int m = 0; m < PTS; ++m) {
-                if (kSkipRows<T> && (row[m] < s || row[m] >= kTileY - s)) continue;
-                const int r = row[m] + 1;  // LDS row (rows 0 and kTileY + 1 are padding)
+                const int r = row[m];
+                if (kSkipRows<T> && (r < s || r >= kRows - s)) continue;
                 res[m] = sweep_point<T>(c[s - 1], kq, lds[s - 1][r][xm], lds[s - 1][r][xp], lds[s - 1][r - 1][lane],
                                         lds[s - 1][r + 1][lane], V[s - 1][vs(s - 1)][m], V[s - 1][vs(s + 1)][m],
                                         V[s - 1][vs(s)][m], Bz[bs(s)][m]);
@@ -288,7 +305,7 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
 #pragma unroll
                 for (int m = 0; m < PTS; ++m) {
                     const int r = row[m];
-                    if (r >= NT && r < kTileY - NT && y0 + r < ny) buf_store(res[m], ro, col[m]);
+                    if (r >= NT && r < kRows - NT && y0 + r < ny) buf_store(res[m], ro, col[m]);
                 }
             }
         }
@@ -296,29 +313,57 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
 #pragma unroll
         for (int s = 0; s < NT; ++s)
 #pragma unroll
-            for (int m = 0; m < PTS; ++m) lds[s][row[m] + 1][lane] = V[s][vs(s)][m];
+            for (int m = 0; m < PTS; ++m) lds[s][row[m]][lane] = V[s][vs(s)][m];
+        if (hrow >= 0) lds[0][hrow][lane] = Vh;
         __syncthreads();
     };
 
     for (int tb = t_begin; tb <= t_end; tb += kUnroll) unrolled(tb, step, std::make_integer_sequence<int, kUnroll>{});
 }
 
+// Workgroups of k_relax_fused<T, NT, WAVES> resident on the device at once.
+template <typename T, int NT, int WAVES>
+int resident_workgroups()
+{
+    static int cached = 0;  // per kernel instance; one device model per process
+    if (cached == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_relax_fused<T, NT, WAVES>, 64 * WAVES, 0) !=
+                hipSuccess)
+            return 0;
+        cached = std::max(1, cus * per_cu);
+    }
+    return cached;
+}
+
 template <typename T, int NT, int WAVES>
 hipError_t launch_fused(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, hipStream_t s)
 {
-    constexpr int OX = kTileX - 2 * NT, OY = kTileY - 2 * NT;
+    constexpr int OX = kTileX - 2 * NT, OY = kRows - 2 * NT;
     const int tx = (g.nx + OX - 1) / OX, ty = (g.ny + OY - 1) / OY;
-    // enough workgroups to fill the 256 CUs, z-chunks of at least
-    // kMinChunk planes (each chunk recomputes NT planes at both ends)
     const long long tiles = (long long)tx * ty;
-    int nzc = (int)std::max<long long>(
-        1, std::min<long long>(g.nz / kMinChunk, (kTargetBlocks + tiles - 1) / tiles));
+    const int resident = resident_workgroups<T, NT, WAVES>();
+    if (resident == 0) return hipErrorInvalidDevice;
+    // z-chunks: the fewest rounds of resident workgroups times steps per
+    // chunk (a chunk of zc planes takes zc + 2 NT steps)
+    int nzc = 1;
+    long long best = -1;
+    for (int k = 1; k <= std::max(1, g.nz / kMinChunk); ++k) {
+        const long long zc = (g.nz + k - 1) / k;
+        const long long cost = (tiles * k + resident - 1) / resident * (zc + 2 * NT);
+        if (best < 0 || cost < best) {
+            best = cost;
+            nzc = k;
+        }
+    }
     const int zchunk = (g.nz + nzc - 1) / nzc;
     nzc = (g.nz + zchunk - 1) / zchunk;
-    const int ntiles = tx * ty * nzc;
+    const int ntiles = (int)(tiles * nzc);
     const int grid = (ntiles + kXcds - 1) / kXcds * kXcds;  // whole rounds over the XCDs
     hipLaunchKernelGGL((k_relax_fused<T, NT, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, g.nx, g.ny, g.nz, zchunk,
-                       tx, ty, ntiles, b, p, out, stage_coefs(g, wts, NT));
+                       tx, ty, ntiles, b, p, out, stage_coefs<T>(g, wts, NT));
     return hipGetLastError();
 }
 
@@ -326,7 +371,7 @@ hipError_t launch_fused(const Geo& g, const T* b, const T* p, T* out, const Weig
 // vertical neighbours in registers; used for grids narrower than a tile.
 template <typename T>
 __global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchunk, const T* __restrict__ b,
-                                               const T* __restrict__ p, T* __restrict__ out, StageCoefs kc)
+                                               const T* __restrict__ p, T* __restrict__ out, StageCoefs<T> kc)
 {
     const Coef<T> c = coef_of<T>(kc, 0);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -363,7 +408,7 @@ hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wt
         if (nfused != 1) return hipErrorInvalidValue;
         const March m = march_shape(g, 2048);
         hipLaunchKernelGGL(k_relax<T>, m.grid, m.block, 0, s, g.nx, g.ny, g.nz, m.kchunk, b, p, out,
-                           stage_coefs(g, wts, 1));
+                           stage_coefs<T>(g, wts, 1));
         return hipGetLastError();
     }
     if (nfused == 2) return launch_fused<T, 2, STP_RELAX_WAVES>(g, b, p, out, wts, s);
