@@ -1,27 +1,29 @@
 // Temporally blocked Jacobi-SOR sweeps for gfx950 (Sec. 3.4: the SRJ cycle
 // is a sequence of weighted Jacobi sweeps p <- p + (omega_s/D)(L_p p - b)).
 //
-// NT consecutive sweeps of the cycle are fused into one launch: every
-// workgroup owns a 64 x 32 column tile of the x-y plane (periodic wrap
-// computed in-kernel) and marches along z.  At each z step it loads one plane
-// of p and b, then advances every stage s = 1..NT of the pipeline by one
-// plane: stage s produces plane t - s from stage s-1's planes t-s-1, t-s,
-// t-s+1.  The vertical neighbours live in per-thread register rings, the x-y
-// neighbours in one LDS plane per stage.  Stage s is exact on points at least
-// s away from the tile edge, so a tile writes its central (64 - 2NT) x
-// (32 - 2NT) columns; a z-chunk is extended by NT planes on each side
-// (clipped at the walls).  Each point evaluates exactly the unblocked formula
-// (sweep_point) in the same order, so NT fused sweeps equal NT single sweeps
-// bit for bit.
+// NT consecutive sweeps of the cycle are fused into one launch.  A workgroup
+// owns a 64 x 34 column tile of the x-y plane (periodic wrap computed
+// in-kernel; rows 1..32 are updated, rows 0 and 33 are only loaded) and
+// marches along z.  At each z step it takes in one plane of p and b, then
+// advances every stage s = 1..NT of the pipeline by one plane: stage s
+// produces plane t - s from stage s-1's planes t-s-1, t-s, t-s+1.  Vertical
+// neighbours live in per-thread register rings, x-y neighbours in LDS planes
+// (double-buffered: one barrier per z step).  Stage s is exact on points at
+// least s away from the tile edge, so a tile writes its central
+// (64 - 2NT) x (34 - 2NT) columns; a z-chunk is extended by NT planes on each
+// side (clipped at the walls).  Each point evaluates exactly the unblocked
+// formula (sweep_point) in the same order, so NT fused sweeps equal NT single
+// sweeps bit for bit.
 //
 // With HBM traffic cut by NT, the kernel is bound by vector-ALU issue and by
-// load latency along the march, which shape the code: the point update is
-// eight instructions with the walls folded into per-plane coefficients (no
-// ghost values, no selects per point); the march is unrolled so that ring
-// slots are static registers and nothing is copied between them; the next
-// plane is requested one step ahead; loads and stores are a 32-bit lane
-// offset on a uniform plane base; in FP32 a stage skips, per wavefront, the
-// rows no later stage reads.
+// latency along the march, which shape the code: the point update is eight
+// instructions with the walls folded into per-plane coefficients (no ghost
+// values, no per-point selects); the march is unrolled so that ring slots are
+// static registers; the next plane is requested one step ahead; loads and
+// stores are a 32-bit lane offset on a uniform plane base; coefficients
+// arrive rounded to the element type so they stay in scalar registers; in
+// FP32 a stage skips, per wavefront, the rows no later stage reads; the tile
+// order is XCD-aware (see k_relax_fused).
 #include "stp_internal.h"
 
 #include <algorithm>
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
     const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
     constexpr int PTS = kTileY / WAVES;  // rows per thread
     constexpr int OX = kTileX - 2 * NT, OY = kRows - 2 * NT;
-    __shared__ T lds[NT][kRows][kTileX];
+    __shared__ T lds[2][NT][kRows][kTileX];  // step t reads buffer (t-1) & 1, writes t & 1
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -264,6 +266,8 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
         auto vs = [](int k) { return ((u - k) % 3 + 3) % 3; };
         auto bs = [](int k) { return ((u - k) % kUnroll + kUnroll) % kUnroll; };
         if (t > t_end) return;
+        auto& rd = lds[(u + 1) & 1];  // planes written by the previous step
+        auto& wr = lds[u & 1];
         // stage 0: plane t arrives; plane t + 1 is requested (the halo row's
         // first: loads complete in order)
         {
@@ -295,8 +299,8 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
             for (int m = 0; m < PTS; ++m) {
                 const int r = row[m];
                 if (kSkipRows<T> && (r < s || r >= kRows - s)) continue;
-                res[m] = sweep_point<T>(c[s - 1], kq, lds[s - 1][r][xm], lds[s - 1][r][xp], lds[s - 1][r - 1][lane],
-                                        lds[s - 1][r + 1][lane], V[s - 1][vs(s - 1)][m], V[s - 1][vs(s + 1)][m],
+                res[m] = sweep_point<T>(c[s - 1], kq, rd[s - 1][r][xm], rd[s - 1][r][xp], rd[s - 1][r - 1][lane],
+                                        rd[s - 1][r + 1][lane], V[s - 1][vs(s - 1)][m], V[s - 1][vs(s + 1)][m],
                                         V[s - 1][vs(s)][m], Bz[bs(s)][m]);
                 if (s < NT) V[s][vs(s)][m] = res[m];
             }
@@ -309,13 +313,12 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
                 }
             }
         }
-        __syncthreads();  // every read of this step's LDS planes is done
 #pragma unroll
         for (int s = 0; s < NT; ++s)
 #pragma unroll
-            for (int m = 0; m < PTS; ++m) lds[s][row[m]][lane] = V[s][vs(s)][m];
-        if (hrow >= 0) lds[0][hrow][lane] = Vh;
-        __syncthreads();
+            for (int m = 0; m < PTS; ++m) wr[s][row[m]][lane] = V[s][vs(s)][m];
+        if (hrow >= 0) wr[0][hrow][lane] = Vh;
+        __syncthreads();  // one barrier: double-buffered planes
     };
 
     for (int tb = t_begin; tb <= t_end; tb += kUnroll) unrolled(tb, step, std::make_integer_sequence<int, kUnroll>{});
