@@ -126,6 +126,35 @@ def test_adam_steps_match_oracle_and_reduce_loss(gpu):
     assert padding_is_zero(params.cpu().numpy(), layout)
 
 
+def test_inference_forward_equals_training_forward(gpu):
+    """Inference reads the decoder's upsampled inputs straight from the coarse
+    tensors; training also materialises them for the weight gradient.  Both
+    forwards give the same guess, bit for bit, on a grid with several tiles,
+    ragged edges and several z-chunks per tile column."""
+    import torch
+    g = (104, 72, 40, 4.0, 3.0, 2.0)
+    print(f"net inference vs training grid={g}", flush=True)
+    p = onet.init_params(seed=9)
+    r = inputs.rng(10)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = 0.05 * r.standard_normal(p[k].shape)
+    b, p_prev, _ = sample(g, 11)
+    outs = []
+    for training in (True, False):
+        from paper_1511_07800_amd import Channel
+        ch = Channel(*g[:3], *g[3:], nu=1.0, dpdx=0.0, dt=1.0)
+        ch.net_init(training=training, seed=0)
+        params, _ = ch.net_params()
+        upload(ch, params, p, ch.net_layout())
+        out = torch.zeros_like(to_dev(torch, b))
+        ch.net_predict(to_dev(torch, b), to_dev(torch, p_prev), out)
+        torch.cuda.synchronize()
+        outs.append(out.cpu())
+    assert torch.equal(outs[0], outs[1])
+    assert float((outs[0] - torch.from_numpy(p_prev)).abs().max()) > 0
+
+
 def test_learned_warm_start_in_step(gpu):
     """STP_WS_LEARNED: the step still reaches the residual target; the guess
     is used only when its residual is smaller than that of p^n."""

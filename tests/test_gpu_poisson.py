@@ -230,6 +230,27 @@ def test_fused_sweeps_equal_single_sweeps_bitwise(gpu, g, dtype, nt):
     assert torch.equal(p1, pf)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fused_sweeps_full_size_bitwise(gpu, dtype):
+    """The 4-sweep launch at the benchmark grid (512x256x192, the launch
+    configuration the bench times: several z-chunks per tile column, ragged
+    last tiles in x and y) equals four single sweeps bit for bit; single sweeps
+    at this size are checked against the oracle in test_full_size_sweep_sampled."""
+    import torch
+    g = (512, 256, 192, 4 * math.pi, 2 * math.pi, 2.0)
+    print(f"fused full size dtype={dtype}", flush=True)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    r = inputs.rng(23)
+    p = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
+    b = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
+    om = [1.3, 57.0, 0.6, 3.1, 11.0, 0.9, 2.2, 40.0]
+    p1, pf = p.clone(), p.clone()
+    channel(g, tblock=1).relax(b, p1, om)
+    channel(g, tblock=4).relax(b, pf, om)
+    torch.cuda.synchronize()
+    assert torch.equal(p1, pf)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solve_with_fused_sweeps_bitwise(gpu, precision):
     import torch
