@@ -28,6 +28,8 @@ struct stp_ctx {
     double* e[3][3] = {};   // Adams-Bashforth history, [slot][component]
     // FP32 work arrays of the mixed solve
     float *e0 = nullptr, *e1 = nullptr, *r32 = nullptr;
+    // FP32 arrays of the mixed-mode Crank-Nicolson solve: nu_T, h L R, increments
+    float *nut32 = nullptr, *cnd = nullptr, *cna = nullptr, *cnb = nullptr;
     double* part = nullptr;  // reduction partials
     double* res = nullptr;   // device scalar results
     double* host = nullptr;  // pinned host copy of res
@@ -44,6 +46,7 @@ struct stp_ctx {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr double kCnTol32 = 1e-7;  // FP32 resolution of the Crank-Nicolson increment
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -94,7 +97,7 @@ const char* validate(const stp_config& c)
 
 // Byte offsets of every array in the workspace.
 struct Layout {
-    size_t u, v, w, p, ptmp, b, nut, rhs[3], tmp, e[3][3], e0, e1, r32, part, res, total;
+    size_t u, v, w, p, ptmp, b, nut, rhs[3], tmp, e[3][3], e0, e1, r32, nut32, cnd, cna, cnb, part, res, total;
 };
 
 Layout layout(const stp_config& c)
@@ -121,6 +124,12 @@ Layout layout(const stp_config& c)
     L.e0 = take(n * 4);
     L.e1 = take(n * 4);
     L.r32 = take(n * 4);
+    if (c.precision == STP_MIXED) {
+        L.nut32 = take(n * 4);
+        L.cnd = take(nw * 4);
+        L.cna = take(nw * 4);
+        L.cnb = take(nw * 4);
+    }
     L.part = take((size_t)kMaxPartBlocks * 8 * 8);
     L.res = take(RES_COUNT * 8);
     L.total = off;
@@ -453,14 +462,38 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
     int mcn = (int)std::ceil(std::log(c.cn_tol) / std::log(rho));
     mcn = std::max(1, std::min(mcn, 999));
     if (mcn % 2 == 0) ++mcn;
-    for (int q = 0; q < 3; ++q) {
-        for (int it = 0; it < mcn; ++it) {
-            const double* x = it == 0 ? ctx->rhs[q] : (it % 2 == 1 ? vel[q] : ctx->tmp);
-            double* xo = it % 2 == 0 ? vel[q] : ctx->tmp;
-            CHK(cn_iterate(g, q, ctx->nut, c.nu, ctx->rhs[q], x, xo, 0.5 * c.dt, 1.0 / (1.0 + hs), s));
+    if (c.precision == STP_MIXED) {
+        // Mixed mode: the defect form u* = R + delta, (I - h L) delta = h L R,
+        // iterated in FP32 from delta = 0 (R and u* stay FP64); FP32 resolves
+        // delta to about 1e-7 of itself, so the target is max(cn_tol, 1e-7).
+        int m32 = (int)std::ceil(std::log(std::max(c.cn_tol, kCnTol32)) / std::log(rho));
+        m32 = std::max(2, std::min(m32, 999));
+        if (c.les) CHK(round_to_f32(ctx->nut32, ctx->nut, g.n, s));
+        else CHK(fill(ctx->nut32, (float)c.nu, g.n, s));
+        for (int q = 0; q < 3; ++q) {
+            float* a = ctx->cna;
+            float* bb = ctx->cnb;
+            CHK(cn_defect(g, q, 0, ctx->nut32, c.nu, ctx->rhs[q], nullptr, ctx->cnd, nullptr, a, nullptr, 0.5 * c.dt,
+                          1.0 / (1.0 + hs), s));
+            for (int it = 1; it + 1 < m32; ++it) {
+                CHK(cn_defect(g, q, 1, ctx->nut32, c.nu, ctx->rhs[q], ctx->cnd, nullptr, a, bb, nullptr, 0.5 * c.dt,
+                              1.0 / (1.0 + hs), s));
+                std::swap(a, bb);
+            }
+            CHK(cn_defect(g, q, 2, ctx->nut32, c.nu, ctx->rhs[q], ctx->cnd, nullptr, a, nullptr, vel[q], 0.5 * c.dt,
+                          1.0 / (1.0 + hs), s));
         }
+        st.cn_sweeps = m32;
+    } else {
+        for (int q = 0; q < 3; ++q) {
+            for (int it = 0; it < mcn; ++it) {
+                const double* x = it == 0 ? ctx->rhs[q] : (it % 2 == 1 ? vel[q] : ctx->tmp);
+                double* xo = it % 2 == 0 ? vel[q] : ctx->tmp;
+                CHK(cn_iterate(g, q, ctx->nut, c.nu, ctx->rhs[q], x, xo, 0.5 * c.dt, 1.0 / (1.0 + hs), s));
+            }
+        }
+        st.cn_sweeps = mcn;
     }
-    st.cn_sweeps = mcn;
 
     // 4. b = div(u*)/dt, mean removed; ||b||^2 into RES_B2
     CHK(divergence_rhs(g, ctx->u, ctx->v, ctx->w, ctx->b, 1.0 / c.dt, ctx->part, ctx->res, s));
@@ -573,6 +606,12 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
     ctx->e0 = (float*)(base + L.e0);
     ctx->e1 = (float*)(base + L.e1);
     ctx->r32 = (float*)(base + L.r32);
+    if (c.precision == STP_MIXED) {
+        ctx->nut32 = (float*)(base + L.nut32);
+        ctx->cnd = (float*)(base + L.cnd);
+        ctx->cna = (float*)(base + L.cna);
+        ctx->cnb = (float*)(base + L.cnb);
+    }
     ctx->part = (double*)(base + L.part);
     ctx->res = (double*)(base + L.res);
     if (c.srj_m > 0) {

@@ -73,6 +73,12 @@ hipError_t momentum_rhs(const Geo& g, int comp, const MomArgs& a, hipStream_t s)
 // One Crank-Nicolson iteration x_out = x + (R - (I - h L) x) * inv_shift.
 hipError_t cn_iterate(const Geo& g, int comp, const double* nut, double nu, const double* rhs, const double* x,
                       double* xout, double half_dt, double inv_shift, hipStream_t s);
+// one Crank-Nicolson iteration in defect form (mixed mode): phase 0 from R,
+// phase 1 delta -> delta, phase 2 delta -> u* = R + delta (FP64)
+hipError_t cn_defect(const Geo& g, int comp, int phase, const float* nut32, double nu, const double* rhs,
+                     const float* d0in, float* d0out, const float* x, float* xo, double* uo, double half_dt,
+                     double inv_shift, hipStream_t s);
+hipError_t round_to_f32(float* dst, const double* src, long long n, hipStream_t s);
 
 hipError_t divergence_rhs(const Geo& g, const double* u, const double* v, const double* w, double* b,
                           double inv_dt, double* part, double* res, hipStream_t s);

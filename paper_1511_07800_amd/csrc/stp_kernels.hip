@@ -237,28 +237,62 @@ __global__ __launch_bounds__(256) void k_nut(Geo g, int kchunk, const double* __
 // ---- momentum: explicit terms and Crank-Nicolson right-hand side (Sec. 3.1)
 
 // Edge viscosities: mean of the four surrounding centres; nu on wall edges.
-struct Nu {
-    const double* __restrict__ t;
+// nu_T at centres (stored as TN) and its averages on edges, evaluated in TC
+template <typename TN, typename TC>
+struct NuT {
+    const TN* __restrict__ t;
     Geo g;
-    double nu;
-    __device__ double c(int i, int j, int k) const { return t[at(g, i, j, k)]; }
+    TC nu;
+    __device__ TC c(int i, int j, int k) const { return (TC)t[at(g, i, j, k)]; }
     // x-y edge between centres (i0|i1) x (j0|j1) on plane k
-    __device__ double xy(int i0, int i1, int j0, int j1, int k) const
+    __device__ TC xy(int i0, int i1, int j0, int j1, int k) const
     {
-        return 0.25 * (c(i0, j0, k) + c(i1, j0, k) + c(i0, j1, k) + c(i1, j1, k));
+        return TC(0.25) * (c(i0, j0, k) + c(i1, j0, k) + c(i0, j1, k) + c(i1, j1, k));
     }
     // x-z edge between centres (i0|i1) x (k-1|k) on row j; wall edges carry nu
-    __device__ double xz(int i0, int i1, int j, int k) const
+    __device__ TC xz(int i0, int i1, int j, int k) const
     {
         if (k <= 0 || k >= g.nz) return nu;
-        return 0.25 * (c(i0, j, k - 1) + c(i1, j, k - 1) + c(i0, j, k) + c(i1, j, k));
+        return TC(0.25) * (c(i0, j, k - 1) + c(i1, j, k - 1) + c(i0, j, k) + c(i1, j, k));
     }
-    __device__ double yz(int i, int j0, int j1, int k) const
+    __device__ TC yz(int i, int j0, int j1, int k) const
     {
         if (k <= 0 || k >= g.nz) return nu;
-        return 0.25 * (c(i, j0, k - 1) + c(i, j1, k - 1) + c(i, j0, k) + c(i, j1, k));
+        return TC(0.25) * (c(i, j0, k - 1) + c(i, j1, k - 1) + c(i, j0, k) + c(i, j1, k));
     }
 };
+using Nu = NuT<double, double>;
+
+// L_nu x = d_j(nu_T d_j x) for velocity component COMP at face (i, j, k)
+// (flat index c), in arithmetic TC: odd ghosts of u, v at the walls; w is
+// not evaluated on its wall planes.
+template <int COMP, typename TC, typename TX, typename TN>
+__device__ __forceinline__ TC visc_apply(const Geo& g, const NuT<TN, TC>& N, const TX* __restrict__ x, long long c,
+                                         int i, int j, int k, int im, int ip, int jm, int jp)
+{
+    const TC xc = (TC)x[c];
+    const TC xE = (TC)x[at(g, ip, j, k)], xW = (TC)x[at(g, im, j, k)];
+    const TC xN = (TC)x[at(g, i, jp, k)], xS = (TC)x[at(g, i, jm, k)];
+    const TC idx2 = (TC)g.idx2, idy2 = (TC)g.idy2, idz2 = (TC)g.idz2;
+    if (COMP == 0) {
+        const TC xT = k + 1 < g.nz ? (TC)x[c + g.plane] : -xc;
+        const TC xB = k > 0 ? (TC)x[c - g.plane] : -xc;
+        return (N.c(i, j, k) * (xE - xc) - N.c(im, j, k) * (xc - xW)) * idx2 +
+               (N.xy(im, i, j, jp, k) * (xN - xc) - N.xy(im, i, jm, j, k) * (xc - xS)) * idy2 +
+               (N.xz(im, i, j, k + 1) * (xT - xc) - N.xz(im, i, j, k) * (xc - xB)) * idz2;
+    } else if (COMP == 1) {
+        const TC xT = k + 1 < g.nz ? (TC)x[c + g.plane] : -xc;
+        const TC xB = k > 0 ? (TC)x[c - g.plane] : -xc;
+        return (N.xy(i, ip, jm, j, k) * (xE - xc) - N.xy(im, i, jm, j, k) * (xc - xW)) * idx2 +
+               (N.c(i, j, k) * (xN - xc) - N.c(i, jm, k) * (xc - xS)) * idy2 +
+               (N.yz(i, jm, j, k + 1) * (xT - xc) - N.yz(i, jm, j, k) * (xc - xB)) * idz2;
+    } else {
+        const TC xT = (TC)x[c + g.plane], xB = (TC)x[c - g.plane];
+        return (N.xz(i, ip, j, k) * (xE - xc) - N.xz(im, i, j, k) * (xc - xW)) * idx2 +
+               (N.yz(i, j, jp, k) * (xN - xc) - N.yz(i, jm, j, k) * (xc - xS)) * idy2 +
+               (N.c(i, j, k) * (xT - xc) - N.c(i, j, k - 1) * (xc - xB)) * idz2;
+    }
+}
 
 // x-momentum on x-faces: E_u = -d_j(u_j u) + d_j(nu_T d_x u_j) - G and
 // R_u = u + dt sum_m beta_m E_u^{n-m} + (dt/2) d_j(nu_T d_j u).
@@ -410,34 +444,65 @@ __global__ __launch_bounds__(256) void k_cn(Geo g, int kchunk, const double* __r
     const int k0 = blockIdx.z * kchunk, k1 = min(nplanes, k0 + kchunk);
     for (int k = k0; k < k1; ++k) {
         const long long c = at(g, i, j, k);
-        const double xc = x[c];
-        const double xE = x[at(g, ip, j, k)], xW = x[at(g, im, j, k)];
-        const double xN = x[at(g, i, jp, k)], xS = x[at(g, i, jm, k)];
-        double L;
-        if (COMP == 0) {
-            const double xT = k + 1 < g.nz ? x[c + g.plane] : -xc;
-            const double xB = k > 0 ? x[c - g.plane] : -xc;
-            L = (N.c(i, j, k) * (xE - xc) - N.c(im, j, k) * (xc - xW)) * g.idx2 +
-                (N.xy(im, i, j, jp, k) * (xN - xc) - N.xy(im, i, jm, j, k) * (xc - xS)) * g.idy2 +
-                (N.xz(im, i, j, k + 1) * (xT - xc) - N.xz(im, i, j, k) * (xc - xB)) * g.idz2;
-        } else if (COMP == 1) {
-            const double xT = k + 1 < g.nz ? x[c + g.plane] : -xc;
-            const double xB = k > 0 ? x[c - g.plane] : -xc;
-            L = (N.xy(i, ip, jm, j, k) * (xE - xc) - N.xy(im, i, jm, j, k) * (xc - xW)) * g.idx2 +
-                (N.c(i, j, k) * (xN - xc) - N.c(i, jm, k) * (xc - xS)) * g.idy2 +
-                (N.yz(i, jm, j, k + 1) * (xT - xc) - N.yz(i, jm, j, k) * (xc - xB)) * g.idz2;
-        } else {
-            if (k == 0 || k == g.nz) {
-                xo[c] = 0.0;
-                continue;
-            }
-            const double xT = x[c + g.plane], xB = x[c - g.plane];
-            L = (N.xz(i, ip, j, k) * (xE - xc) - N.xz(im, i, j, k) * (xc - xW)) * g.idx2 +
-                (N.yz(i, j, jp, k) * (xN - xc) - N.yz(i, jm, j, k) * (xc - xS)) * g.idy2 +
-                (N.c(i, j, k) * (xT - xc) - N.c(i, j, k - 1) * (xc - xB)) * g.idz2;
+        if (COMP == 2 && (k == 0 || k == g.nz)) {
+            xo[c] = 0.0;
+            continue;
         }
+        const double xc = x[c];
+        const double L = visc_apply<COMP, double>(g, N, x, c, i, j, k, im, ip, jm, jp);
         xo[c] = xc + (R[c] - xc + h * L) * inv_shift;
     }
+}
+
+// Crank-Nicolson solve in defect form for the mixed mode: u* = R + delta with
+// (I - h L) delta = h L R, so that the iterate is the small viscous increment
+// and FP32 resolves it; R and u* stay FP64.  From delta = 0, one step of the
+// same iteration as k_cn per launch:
+//   PHASE 0: d0 = h L R (FP64 arithmetic, FP32 nu_T), delta_1 = d0 / (1 + h s)
+//   PHASE 1: delta_out = delta + (d0 - delta + h L delta) / (1 + h s)  (FP32)
+//   PHASE 2: as PHASE 1, then u* = R + delta_out in FP64.
+template <int COMP, int PHASE>
+__global__ __launch_bounds__(256) void k_cn_defect(Geo g, int kchunk, const float* __restrict__ nut32, double nu,
+                                                   const double* __restrict__ R, const float* __restrict__ d0in,
+                                                   float* __restrict__ d0out, const float* __restrict__ x,
+                                                   float* __restrict__ xo, double* __restrict__ uo, double h,
+                                                   double inv_shift)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
+    const NuT<float, double> Nd{nut32, g, nu};
+    const NuT<float, float> Nf{nut32, g, (float)nu};
+    const float h32 = (float)h, inv32 = (float)inv_shift;
+    const int nplanes = COMP == 2 ? g.nz + 1 : g.nz;
+    const int k0 = blockIdx.z * kchunk, k1 = min(nplanes, k0 + kchunk);
+    for (int k = k0; k < k1; ++k) {
+        const long long c = at(g, i, j, k);
+        if (COMP == 2 && (k == 0 || k == g.nz)) {
+            if (PHASE == 0) d0out[c] = 0.f;
+            if (PHASE < 2) xo[c] = 0.f;
+            else uo[c] = 0.0;
+            continue;
+        }
+        if (PHASE == 0) {
+            const float d = (float)(h * visc_apply<COMP, double>(g, Nd, R, c, i, j, k, im, ip, jm, jp));
+            d0out[c] = d;
+            xo[c] = d * inv32;
+        } else {
+            const float xc = x[c];
+            const float L = visc_apply<COMP, float>(g, Nf, x, c, i, j, k, im, ip, jm, jp);
+            const float xn = xc + (d0in[c] - xc + h32 * L) * inv32;
+            if (PHASE == 1) xo[c] = xn;
+            else uo[c] = R[c] + (double)xn;
+        }
+    }
+}
+
+__global__ void k_round32(float* __restrict__ d, const double* __restrict__ s, long long n)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        d[q] = (float)s[q];
 }
 
 // ---- divergence, Poisson right-hand side (Sec. 3.1) -------------------------
@@ -651,6 +716,30 @@ hipError_t cn_iterate(const Geo& g, int comp, const double* nut, double nu, cons
         hipLaunchKernelGGL(k_cn<1>, m.grid, m.block, 0, s, g, m.kchunk, nut, nu, rhs, x, xout, half_dt, inv_shift);
     else
         hipLaunchKernelGGL(k_cn<2>, m.grid, m.block, 0, s, g, m.kchunk, nut, nu, rhs, x, xout, half_dt, inv_shift);
+    return hipGetLastError();
+}
+
+hipError_t cn_defect(const Geo& g, int comp, int phase, const float* nut32, double nu, const double* rhs,
+                     const float* d0in, float* d0out, const float* x, float* xo, double* uo, double half_dt,
+                     double inv_shift, hipStream_t s)
+{
+    Geo gw = g;  // w has nz + 1 planes
+    if (comp == 2) gw.nz = g.nz + 1;
+    const March m = march_shape(gw, 2048);
+#define STP_CND(C, P)                                                                                             \
+    hipLaunchKernelGGL((k_cn_defect<C, P>), m.grid, m.block, 0, s, g, m.kchunk, nut32, nu, rhs, d0in, d0out, x, xo, \
+                       uo, half_dt, inv_shift)
+    if (comp < 0 || comp > 2 || phase < 0 || phase > 2) return hipErrorInvalidValue;
+    if (comp == 0) { if (phase == 0) STP_CND(0, 0); else if (phase == 1) STP_CND(0, 1); else STP_CND(0, 2); }
+    if (comp == 1) { if (phase == 0) STP_CND(1, 0); else if (phase == 1) STP_CND(1, 1); else STP_CND(1, 2); }
+    if (comp == 2) { if (phase == 0) STP_CND(2, 0); else if (phase == 1) STP_CND(2, 1); else STP_CND(2, 2); }
+#undef STP_CND
+    return hipGetLastError();
+}
+
+hipError_t round_to_f32(float* dst, const double* src, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_round32, dim3(grid1d(n)), dim3(kBlock1d), 0, s, dst, src, n);
     return hipGetLastError();
 }
 
