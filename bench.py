@@ -194,7 +194,7 @@ def main():
         fp64 = {"steps_per_s": round(args.steps / t64, 4), "ms_per_step": round(1e3 * t64 / args.steps, 2),
                 "sweeps_per_step": acc64["sweeps"] / args.steps,
                 "gcell_updates_per_s": round(acc64["sweeps"] * n / t64 / 1e9, 2),
-                "relax_kernel": roofline_from_steps(n, acc64, 8, "k_relax_fused<double,4,8>")}
+                "relax_kernel": roofline_from_steps(n, acc64, 8, "k_relax_fused<double,4,16>")}
         ch.close()
         del ch
         torch.cuda.empty_cache()

@@ -21,9 +21,9 @@
 // values, no per-point selects); the march is unrolled so that ring slots are
 // static registers; the next plane is requested one step ahead; loads and
 // stores are a 32-bit lane offset on a uniform plane base; coefficients
-// arrive rounded to the element type so they stay in scalar registers; in
-// FP32 a stage skips, per wavefront, the rows no later stage reads; the tile
-// order is XCD-aware (see k_relax_fused).
+// arrive rounded to the element type so they stay in scalar registers; every
+// stage updates all 32 rows (straight-line code; rows a later stage does not
+// read are discarded); the tile order is XCD-aware (see k_relax_fused).
 #include "stp_internal.h"
 
 #include <algorithm>
@@ -39,9 +39,10 @@ constexpr int kTileY = 32;  // rows updated by a workgroup; two more halo rows a
 constexpr int kRows = kTileY + 2;
 static int kMinChunk = 8;  // planes per z-chunk, at least
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X, each with its own L2
-#ifndef STP_RELAX_WAVES
-#define STP_RELAX_WAVES 8      // wavefronts per workgroup; kTileY / waves rows per thread
-#endif
+// wavefronts per workgroup (kTileY / waves rows per thread): measured best
+// 8 for FP32 (two workgroups per CU under the 128-VGPR cap) and 16 for FP64
+template <typename T>
+constexpr int kWaves = sizeof(T) == 4 ? 8 : 16;
 
 // Coefficients of one weighted Jacobi sweep, from omega and D = 2/dx^2 +
 // 2/dy^2 + 2/dz^2:  p + (omega/D)(L_p p - b)
@@ -161,12 +162,8 @@ __device__ __forceinline__ void unrolled(int t0, F& f, std::integer_sequence<int
     (f(t0 + U, std::integral_constant<int, U>{}), ...);
 }
 
-// FP32: skip the rows a stage does not need (wave-uniform branches) and cap
-// the kernel at 128 VGPRs so two workgroups share a CU.  FP64: the rings
-// need about 200 VGPRs, one workgroup per CU, and straight-line code without
-// the row branches measured faster.
-template <typename T>
-constexpr bool kSkipRows = sizeof(T) == 4;
+// FP32 is capped at 128 VGPRs so two workgroups share a CU; FP64 needs about
+// 200 VGPRs, one workgroup per CU.
 template <typename T>
 constexpr int kMinWavesPerSimd = sizeof(T) == 4 ? 4 : 1;
 
@@ -285,10 +282,10 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
             }
         }
         // stages 1..NT: stage s produces plane q = t - s from stage s-1's
-        // planes q + 1, q, q - 1.  Stage s is needed only on rows [s, 32 - s)
-        // and planes [z0 - (NT - s), z1 + (NT - s)) inside the walls; both
-        // tests are uniform per wavefront.  Rows outside that range (when not
-        // skipped) read the padding rows of LDS and are never used.
+        // planes q + 1, q, q - 1.  Stage s is needed only on tile rows
+        // [s, 34 - s) and on planes [z0 - (NT - s), z1 + (NT - s)) inside the
+        // walls; planes outside are skipped (a uniform test), rows outside are
+        // computed from neighbours that are not valid and never read.
 #pragma unroll
         for (int s = 1; s <= NT; ++s) {
             const int q = t - s;
@@ -298,7 +295,6 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
 #pragma unroll
             for (int m = 0; m < PTS; ++m) {
                 const int r = row[m];
-                if (kSkipRows<T> && (r < s || r >= kRows - s)) continue;
                 res[m] = sweep_point<T>(c[s - 1], kq, rd[s - 1][r][xm], rd[s - 1][r][xp], rd[s - 1][r - 1][lane],
                                         rd[s - 1][r + 1][lane], V[s - 1][vs(s - 1)][m], V[s - 1][vs(s + 1)][m],
                                         V[s - 1][vs(s)][m], Bz[bs(s)][m]);
@@ -414,8 +410,8 @@ hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wt
                            stage_coefs<T>(g, wts, 1));
         return hipGetLastError();
     }
-    if (nfused == 2) return launch_fused<T, 2, STP_RELAX_WAVES>(g, b, p, out, wts, s);
-    if (nfused == 4) return launch_fused<T, 4, STP_RELAX_WAVES>(g, b, p, out, wts, s);
+    if (nfused == 2) return launch_fused<T, 2, kWaves<T>>(g, b, p, out, wts, s);
+    if (nfused == 4) return launch_fused<T, 4, kWaves<T>>(g, b, p, out, wts, s);
     return hipErrorInvalidValue;
 }
 template hipError_t relax<double>(const Geo&, const double*, const double*, double*, const Weights&, int, hipStream_t);
