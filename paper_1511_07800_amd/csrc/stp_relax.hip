@@ -7,7 +7,8 @@
 // marches along z.  At each z step it takes in one plane of p and b, then
 // advances every stage s = 1..NT of the pipeline by one plane: stage s
 // produces plane t - s from stage s-1's planes t-s-1, t-s, t-s+1.  Vertical
-// neighbours live in per-thread register rings, x-y neighbours in LDS planes
+// neighbours live in per-thread register rings, x neighbours in the next
+// lanes' registers (DPP wave shifts), y neighbours in LDS planes
 // (double-buffered: one barrier per z step).  Stage s is exact on points at
 // least s away from the tile edge, so a tile writes its central
 // (64 - 2NT) x (34 - 2NT) columns; a z-chunk is extended by NT planes on each
@@ -155,6 +156,31 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, un
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
 
+// value of the lane below / above in the wavefront (DPP wave shifts); the
+// end lanes get 0, as they lie in the tile's halo
+__device__ __forceinline__ float lane_from_below(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_from_above(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double lane_from_below(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_from_above(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
 // f(t0 + U, U) for U = 0, 1, ..., in order, with U a compile-time constant
 template <typename F, int... U>
 __device__ __forceinline__ void unrolled(int t0, F& f, std::integer_sequence<int, U...>)
@@ -210,7 +236,6 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
     }
     const int hrow = wave == 0 ? 0 : (wave == WAVES - 1 ? kRows - 1 : -1);  // uniform per wavefront
     const unsigned hcol = (unsigned)(((((y0 + max(hrow, 0)) % ny + ny) % ny) * nx + gx)) * (unsigned)sizeof(T);
-    const int xm = max(lane - 1, 0), xp = min(lane + 1, kTileX - 1);
     const bool out_x = lane >= NT && lane < kTileX - NT && x0 + lane < nx;
 
     Coef<T> c[NT];
@@ -295,9 +320,11 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
 #pragma unroll
             for (int m = 0; m < PTS; ++m) {
                 const int r = row[m];
-                res[m] = sweep_point<T>(c[s - 1], kq, rd[s - 1][r][xm], rd[s - 1][r][xp], rd[s - 1][r - 1][lane],
-                                        rd[s - 1][r + 1][lane], V[s - 1][vs(s - 1)][m], V[s - 1][vs(s + 1)][m],
-                                        V[s - 1][vs(s)][m], Bz[bs(s)][m]);
+                // x neighbours: the centre register of the neighbouring lanes
+                const T pcm = V[s - 1][vs(s)][m];
+                res[m] = sweep_point<T>(c[s - 1], kq, lane_from_below(pcm), lane_from_above(pcm),
+                                        rd[s - 1][r - 1][lane], rd[s - 1][r + 1][lane], V[s - 1][vs(s - 1)][m],
+                                        V[s - 1][vs(s + 1)][m], pcm, Bz[bs(s)][m]);
                 if (s < NT) V[s][vs(s)][m] = res[m];
             }
             if (s == NT && q >= z0 && out_x) {
