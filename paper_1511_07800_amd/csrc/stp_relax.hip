@@ -6,10 +6,12 @@
 // in-kernel; rows 1..32 are updated, rows 0 and 33 are only loaded) and
 // marches along z.  At each z step it takes in one plane of p and b, then
 // advances every stage s = 1..NT of the pipeline by one plane: stage s
-// produces plane t - s from stage s-1's planes t-s-1, t-s, t-s+1.  Vertical
-// neighbours live in per-thread register rings, x neighbours in the next
-// lanes' registers (DPP wave shifts), y neighbours in LDS planes
-// (double-buffered: one barrier per z step).  Stage s is exact on points at
+// produces plane t - s from stage s-1's planes t-s-1, t-s, t-s+1.  A
+// wavefront owns 32/waves contiguous rows: z neighbours live in per-thread
+// register rings, x neighbours in the next lanes' registers (DPP wave
+// shifts), y neighbours in the thread's own adjacent rows, except across
+// wavefronts, where the boundary rows go through LDS planes (double-buffered:
+// one barrier per z step).  Stage s is exact on points at
 // least s away from the tile edge, so a tile writes its central
 // (64 - 2NT) x (34 - 2NT) columns; a z-chunk is extended by NT planes on each
 // side (clipped at the walls).  Each point evaluates exactly the unblocked
@@ -223,14 +225,14 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
     const int gx = ((x0 + lane) % nx + nx) % nx;
     // byte offset of this thread's column within a plane: a 32-bit vector
     // offset on a uniform plane address (planes below 4 GiB)
-    // Tile rows 1..kTileY are updated (row[m] = 1 + wave + WAVES m); rows 0
+    // Tile rows 1..kTileY are updated (row[m] = 1 + wave PTS + m); rows 0
     // and kRows - 1 are the y halo of the first stage, loaded by the first
     // and the last wavefront and never updated.
     unsigned col[PTS];
     int row[PTS];
 #pragma unroll
     for (int m = 0; m < PTS; ++m) {
-        row[m] = 1 + wave + WAVES * m;
+        row[m] = 1 + wave * PTS + m;
         const int gy = ((y0 + row[m]) % ny + ny) % ny;
         col[m] = (unsigned)(gy * nx + gx) * (unsigned)sizeof(T);
     }
@@ -322,9 +324,13 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
                 const int r = row[m];
                 // x neighbours: the centre register of the neighbouring lanes
                 const T pcm = V[s - 1][vs(s)][m];
-                res[m] = sweep_point<T>(c[s - 1], kq, lane_from_below(pcm), lane_from_above(pcm),
-                                        rd[s - 1][r - 1][lane], rd[s - 1][r + 1][lane], V[s - 1][vs(s - 1)][m],
-                                        V[s - 1][vs(s + 1)][m], pcm, Bz[bs(s)][m]);
+                // y neighbours: this thread's adjacent rows, or (at the
+                // wavefront's first and last row) the neighbouring wavefront's
+                // row through LDS
+                const T ps = m > 0 ? V[s - 1][vs(s)][m > 0 ? m - 1 : 0] : rd[s - 1][r - 1][lane];
+                const T pn = m + 1 < PTS ? V[s - 1][vs(s)][m + 1 < PTS ? m + 1 : 0] : rd[s - 1][r + 1][lane];
+                res[m] = sweep_point<T>(c[s - 1], kq, lane_from_below(pcm), lane_from_above(pcm), ps, pn,
+                                        V[s - 1][vs(s - 1)][m], V[s - 1][vs(s + 1)][m], pcm, Bz[bs(s)][m]);
                 if (s < NT) V[s][vs(s)][m] = res[m];
             }
             if (s == NT && q >= z0 && out_x) {
@@ -339,7 +345,8 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
 #pragma unroll
         for (int s = 0; s < NT; ++s)
 #pragma unroll
-            for (int m = 0; m < PTS; ++m) wr[s][row[m]][lane] = V[s][vs(s)][m];
+            for (int m = 0; m < PTS; ++m)
+                if (m == 0 || m == PTS - 1) wr[s][row[m]][lane] = V[s][vs(s)][m];  // rows other wavefronts read
         if (hrow >= 0) wr[0][hrow][lane] = Vh;
         __syncthreads();  // one barrier: double-buffered planes
     };
