@@ -44,12 +44,13 @@ def parse():
     return ap.parse_args()
 
 
-def make_channel(wl, precision, rtol, warm_start=0):
+def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0):
     import torch
     from paper_1511_07800_amd import Channel, inputs
     ch = Channel(wl["nx"], wl["ny"], wl["nz"], wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"],
                  dt=wl["dt"], les=wl["les"], cs=wl.get("cs", 0.1), vd_a=wl.get("vd_a", 25.0), precision=precision,
-                 poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=0 if FIXED_CYCLES else 1)
+                 poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=0 if FIXED_CYCLES else 1,
+                 learned_correction=learned_correction)
     u, v, w = inputs.channel_state(wl["nx"], wl["ny"], wl["nz"], wl["lz"], wl["nu"], wl["dpdx"],
                                    noise=wl.get("noise", 0.0), seed=wl.get("seed", 0))
     for k, a in enumerate((u, v, w)):
@@ -68,7 +69,7 @@ def time_steps(ch, steps, warmup, label):
         print(f"[{label}] warmup step {i + 1}/{warmup}: sweeps {st['poisson']['sweeps']} "
               f"relres0 {st['poisson']['relres0']:.2e} cfl {st['cfl']:.3f}", flush=True)
     torch.cuda.synchronize()
-    acc = {"sweeps": 0, "launches": 0, "ms_relax": 0.0}
+    acc = {"sweeps": 0, "launches": 0, "ms_relax": 0.0, "corrections": 0}
     t0 = time.perf_counter()
     for i in range(steps):
         st = ch.step(1)
@@ -77,7 +78,9 @@ def time_steps(ch, steps, warmup, label):
         print(f"[{label}] step {i + 1}/{steps}: sweeps {st['poisson']['sweeps']} outer {st['poisson']['outer']} "
               f"relres0 {st['poisson']['relres0']:.2e} relres {st['poisson']['relres']:.2e} "
               f"ms {st['ms_total']:.1f} (poisson {st['ms_poisson']:.1f}, sweeps {st['poisson']['ms_relax']:.1f}) "
-              f"max_div {st['max_div']:.1e}" + (f" net {st['ms_net']:.1f} ms relres p^n {st['relres_prev']:.2e} "
+              f"max_div {st['max_div']:.1e}" + (f" corrections {st['poisson']['corrections']}"
+                                                 if st['poisson']['corrections'] else "") +
+              (f" net {st['ms_net']:.1f} ms relres p^n {st['relres_prev']:.2e} "
                                                  f"guess {st['relres_learned']:.2e}" if st['ms_net'] > 0 else ""),
               flush=True)
     torch.cuda.synchronize()
@@ -201,17 +204,19 @@ def main():
 
     learned = None
     learned_256 = None
+    learned_cc = None
     if not args.no_learned:
         from paper_1511_07800_amd import STP_WS_LEARNED, warmstart
 
-        def run_learned(weights, label):
-            ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED)
+        def run_learned(weights, label, correction=0):
+            ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED, learned_correction=correction)
             ch.net_init(training=False)
             warmstart.load_weights(ch, weights)
             tl, accl, stl = time_steps(ch, args.steps, args.warmup, label)
             out = {"steps_per_s": round(args.steps / tl, 4), "ms_per_step": round(1e3 * tl / args.steps, 2),
                    "sweeps_per_step": accl["sweeps"] / args.steps, "ms_net_last": round(stl["ms_net"], 2),
                    "relres_prev_last": stl["relres_prev"], "relres_learned_last": stl["relres_learned"],
+                   "corrections_per_step": accl["corrections"] / args.steps,
                    "weights": os.path.relpath(weights, ROOT)}
             ch.close()
             torch.cuda.empty_cache()
@@ -220,6 +225,7 @@ def main():
         wdir = os.path.join(ROOT, "paper_1511_07800_amd", "weights")
         learned = run_learned(os.path.join(wdir, "warmstart_les512.npy"), "learned+mixed")
         learned_256 = run_learned(os.path.join(wdir, "warmstart_les.npy"), "learned(256-trained)+mixed")
+        learned_cc = run_learned(os.path.join(wdir, "warmstart_les512.npy"), "learned+correction+mixed", correction=1)
 
     roof = roofline_from_steps(n, acc_mixed, 4, "k_relax_fused<float,4,8>")
     roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
@@ -235,13 +241,16 @@ def main():
                    "poisson_rtol": args.rtol, "dt": wl["dt"], "les": wl["les"], "init": "laminar+10% noise",
                    "srj_cycles": "fixed 1e-3" if FIXED_CYCLES else "adaptive"},
         "les_steps_per_s": {"mixed": round(args.steps / t_mixed, 4), "fp64": fp64["steps_per_s"] if fp64 else None,
-                            "learned_mixed": learned["steps_per_s"] if learned else None},
+                            "learned_mixed": learned["steps_per_s"] if learned else None,
+                            "learned_mixed_correction": learned_cc["steps_per_s"] if learned_cc else None},
         "sweeps_per_step": {"mixed": acc_mixed["sweeps"] / args.steps,
                             "fp64": fp64["sweeps_per_step"] if fp64 else None,
-                            "learned_mixed": learned["sweeps_per_step"] if learned else None},
+                            "learned_mixed": learned["sweeps_per_step"] if learned else None,
+                            "learned_mixed_correction": learned_cc["sweeps_per_step"] if learned_cc else None},
         "fp64": fp64,
         "learned_mixed": learned,
         "learned_mixed_trained_256x128x128": learned_256,
+        "learned_mixed_correction": learned_cc,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

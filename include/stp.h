@@ -112,6 +112,10 @@ typedef struct {
                                   nx < 64 or ny < 32 always run single sweeps.  Results are bitwise
                                   identical for every value. */
     double cn_tol;             /* Crank-Nicolson iteration error target relative to the start (e.g. 1e-13) */
+    int32_t learned_correction; /* mixed mode with stp_net_init: after each defect-correction pass that has
+                                   not converged, try p + s_r y(r, p) from the network (a coarse
+                                   correction of the residual r) and keep it when its FP64 residual is
+                                   smaller; the stop test is unchanged.  0: off.  Not used in FP64 mode. */
     void* stream;              /* hipStream_t for all work */
 } stp_config;
 
@@ -124,7 +128,7 @@ typedef struct {
     double relres;     /* after the solve */
     double bnorm;      /* ||b||_2 */
     int32_t launches;  /* relaxation kernel launches (each runs tblock sweeps or fewer) */
-    int32_t pad;
+    int32_t corrections; /* learned coarse corrections kept (learned_correction) */
     double ms_relax;   /* device time of the back-to-back sweep sequences (events around each), ms */
 } stp_solve_stats;
 

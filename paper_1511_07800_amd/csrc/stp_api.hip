@@ -92,6 +92,7 @@ const char* validate(const stp_config& c)
     if (c.srj_adaptive && c.srj_m > 0) return "srj_adaptive needs the built-in schedule (srj_m = 0)";
     if (c.tblock != 1 && c.tblock != 2 && c.tblock != 4) return "tblock must be 1, 2 or 4";
     if (!(c.cn_tol > 0.0 && c.cn_tol < 1.0)) return "cn_tol must lie in (0, 1)";
+    if (c.learned_correction != 0 && c.learned_correction != 1) return "learned_correction must be 0 or 1";
     return nullptr;
 }
 
@@ -377,11 +378,33 @@ stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, in
         ++outer;
         return STP_OK;
     };
+    // Learned coarse correction: the network maps the residual r of p to an
+    // estimate of L^-1 r; the proposal p + s_r y replaces p only when its FP64
+    // residual is smaller (r32 is left holding the residual of whichever is kept).
+    int corrections = 0;
+    auto correct = [&]() -> stp_status {
+        CHK(ctx->net->predict(b, p, ctx->ptmp));
+        CHK(residual(ctx->g, b, ctx->ptmp, ctx->r32, ctx->part, ctx->res, ctx->s));
+        stp_status r2 = readback(ctx);
+        if (r2 != STP_OK) return r2;
+        const double rg = std::sqrt(ctx->host[RES_R2]);
+        if (std::isfinite(rg) && rg < rn) {
+            CHK(copy(p, ctx->ptmp, ctx->g.n, ctx->s));
+            rn = rg;
+            ++corrections;
+        } else {
+            CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s));
+        }
+        return STP_OK;
+    };
+    const bool learned = ctx->cfg.learned_correction && ctx->net != nullptr;
     if (rtol > 0.0) {
         while (!(rn <= rtol * fb)) {
             if (!std::isfinite(rn)) { st->status = STP_ENAN; break; }
             if (outer >= maxit) { st->status = STP_ENOCONV; break; }
             if ((rc = pass()) != STP_OK) return rc;
+            if (learned && !(rn <= rtol * fb) && std::isfinite(rn) && outer < maxit)
+                if ((rc = correct()) != STP_OK) return rc;
         }
     } else {
         for (int it = 0; it < maxit; ++it)
@@ -393,6 +416,7 @@ stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, in
     st->relres = rn / fb;
     st->cycles = outer * inner;
     st->outer = outer;
+    st->corrections = corrections;
     st->sweeps = (int32_t)sweeps;
     return STP_OK;
 }

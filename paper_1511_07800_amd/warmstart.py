@@ -23,11 +23,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart_les.npy")
 
 
-def make_channel(wl, precision=STP_MIXED, rtol=1e-8, warm_start=STP_WS_PREV, seed=None, srj_adaptive=0):
+def make_channel(wl, precision=STP_MIXED, rtol=1e-8, warm_start=STP_WS_PREV, seed=None, srj_adaptive=0,
+                 learned_correction=0):
     import torch
     ch = Channel(wl["nx"], wl["ny"], wl["nz"], wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"],
                  dt=wl["dt"], les=wl["les"], cs=wl.get("cs", 0.1), vd_a=wl.get("vd_a", 25.0), precision=precision,
-                 poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=srj_adaptive)
+                 poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=srj_adaptive,
+                 learned_correction=learned_correction)
     u, v, w = inputs.channel_state(wl["nx"], wl["ny"], wl["nz"], wl["lz"], wl["nu"], wl["dpdx"],
                                    noise=wl.get("noise", 0.0), seed=wl.get("seed", 0) if seed is None else seed)
     for k, a in enumerate((u, v, w)):

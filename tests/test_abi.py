@@ -80,3 +80,32 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(b, "_LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(ImportError):
         b.load_library()
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    """The binding's ctypes structures have the sizes and field offsets a C
+    compiler gives the structs of include/stp.h."""
+    import shutil
+    import subprocess
+    from paper_1511_07800_amd import Config
+    from paper_1511_07800_amd.binding import SolveStats, StepStats
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"stp_config": Config, "stp_solve_stats": SolveStats, "stp_step_stats": StepStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "stp.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -37,6 +37,33 @@ def test_trained_network_saves_sweeps_on_unseen_flow(gpu):
     assert res[STP_WS_LEARNED]["sweeps"] < res[STP_WS_PREV]["sweeps"]
 
 
+def test_learned_coarse_correction_saves_sweeps(gpu):
+    """The same network used as a coarse correction between the mixed
+    solve's defect-correction passes: each proposal is kept only when it
+    lowers the FP64 residual, the stop test is unchanged, and fewer sweeps
+    reach it than with the warm start alone."""
+    wl = workloads.params("les_channel_256x128x128")
+    res = {}
+    for corr in (0, 1):
+        ch = warmstart.make_channel(wl, STP_MIXED, 1e-8, warm_start=STP_WS_LEARNED, seed=9100,
+                                    learned_correction=corr)
+        ch.net_init(training=False)
+        warmstart.load_weights(ch)
+        ch.step(20)
+        sweeps, kept = [], []
+        for _ in range(10):
+            st = ch.step(1)
+            assert st["poisson"]["relres"] <= 1e-8
+            sweeps.append(st["poisson"]["sweeps"])
+            kept.append(st["poisson"]["corrections"])
+        res[corr] = dict(sweeps=np.mean(sweeps), corrections=np.mean(kept))
+        ch.close()
+    print("coarse correction:", res)
+    assert res[0]["corrections"] == 0
+    assert res[1]["corrections"] >= 1
+    assert res[1]["sweeps"] < res[0]["sweeps"]
+
+
 def test_training_from_scratch_improves_guess(gpu):
     """Train a fresh network on a small LES (64x32x32) with the project's own
     kernels; on held-out later steps its guess beats p^n."""
