@@ -30,8 +30,8 @@ FIXED_CYCLES = False  # set by --fixed-cycles: repeat the 1e-3 cycle instead of 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", default="les_channel_512x256x192")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")

@@ -90,7 +90,7 @@ const char* validate(const stp_config& c)
     if (c.mixed_inner < 1) return "mixed_inner must be >= 1";
     if (c.srj_adaptive != 0 && c.srj_adaptive != 1) return "srj_adaptive must be 0 or 1";
     if (c.srj_adaptive && c.srj_m > 0) return "srj_adaptive needs the built-in schedule (srj_m = 0)";
-    if (c.tblock != 1 && c.tblock != 2 && c.tblock != 4) return "tblock must be 1, 2 or 4";
+    if (c.tblock < 1 || c.tblock > kMaxFused) return "tblock must lie in 1..5";
     if (!(c.cn_tol > 0.0 && c.cn_tol < 1.0)) return "cn_tol must lie in (0, 1)";
     if (c.learned_correction != 0 && c.learned_correction != 1) return "learned_correction must be 0 or 1";
     return nullptr;
@@ -251,13 +251,12 @@ template <typename T>
 stp_status run_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, const double* omega, int m, long long first,
                       long long count, int* launches = nullptr)
 {
-    // NT sweeps per launch where the grid allows it; a remainder of 2 or 3
-    // sweeps uses one fused pair, the rest single sweeps.
-    const int tb = relax_fusable(ctx->g) ? ctx->cfg.tblock : 1;
+    // tblock sweeps per launch where the grid allows it (FP64: at most 4),
+    // the remainder in one shorter launch.
+    const int tb = relax_fusable(ctx->g) ? std::min(ctx->cfg.tblock, sizeof(T) == 4 ? kMaxFused : 4) : 1;
     long long s = 0;
     while (s < count) {
-        const long long left = count - s;
-        const int nf = left >= tb ? tb : (left >= 2 && tb >= 2 ? 2 : 1);
+        const int nf = (int)std::min<long long>(tb, count - s);
         Weights wts{};
         for (int f = 0; f < nf; ++f) wts.omega[f] = omega[(first + s + f) % m];
         CHK(relax<T>(ctx->g, b, *cur, *other, wts, nf, ctx->s));

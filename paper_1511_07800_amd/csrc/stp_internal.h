@@ -40,7 +40,7 @@ enum ResSlot {
 };
 
 constexpr int kMaxPartBlocks = 65536;  // partial-sum slots per reduced quantity
-constexpr int kMaxFused = 4;           // sweeps fused per relaxation launch
+constexpr int kMaxFused = 5;           // sweeps fused per relaxation launch (FP64: 4)
 
 struct Weights {  // omega_s of the fused sweeps of one launch
     double omega[kMaxFused];
@@ -86,7 +86,8 @@ hipError_t remove_mean(double* a, long long n, const double* res_sum, int res_ou
                        hipStream_t s);  // a -= res_sum[0]/n; optional sum of squares into res[res_out_sq]
 hipError_t sum_into(const double* a, long long n, double* part, double* res, int slot, hipStream_t s);
 
-// nfused = 1 (any grid) or 2, 4 (grids with nx >= 64 and ny >= 32).
+// nfused = 1 (any grid) or 2..kMaxFused (FP64: 2..4) on grids with nx >= 64
+// and ny >= 32.
 bool relax_fusable(const Geo& g);
 template <typename T>
 hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, int nfused, hipStream_t s);

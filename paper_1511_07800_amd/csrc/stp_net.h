@@ -53,6 +53,9 @@ private:
     long long nv_[3];
     double D_, idx2_, idy2_, idz2_;
     bool training_;
+    // channels per cell of the input tensor X: training's weight gradient of
+    // the first layer reads 16, inference only the 8 the first layer uses
+    int xstride() const { return training_ ? 16 : 8; }
     hipStream_t s_;
     NetLayer L_[kLayers];
     long long nparam_ = 0, nwb_ = 0;

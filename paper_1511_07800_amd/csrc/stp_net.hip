@@ -16,6 +16,7 @@
 #include "stp_net.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 namespace stp {
@@ -30,13 +31,8 @@ struct Lvl {
     long long n;
 };
 
-__device__ __forceinline__ uint16_t f2bf(float f)
-{
-    unsigned u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);                                           // round to nearest even
-    return (uint16_t)(u >> 16);
-}
+// round to nearest even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((unsigned)h << 16); }
 
 __device__ __forceinline__ void cell_xyz(const Lvl& L, long long v, int& x, int& y, int& z)
@@ -140,23 +136,24 @@ __global__ __launch_bounds__(256) void k_scale_from(const double* __restrict__ p
     }
 }
 
-// X[v] = (r/(D s_r), (p - mean)/s_p, 0 x 14) in BF16
+// X[v] = (r/(D s_r), (p - mean)/s_p, 0 ...) in BF16, xstride (8 or 16) channels per cell
 __global__ void k_normalise(LapGeo G, const double* __restrict__ b, const double* __restrict__ p, long long n,
-                            double invD, const double* __restrict__ sc, uint16_t* __restrict__ X)
+                            double invD, const double* __restrict__ sc, uint16_t* __restrict__ X, int xstride)
 {
     const double m = sc[0], sr = sc[1], sp = sc[3];
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
     for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
-        uint16_t* o = X + v * 16;
-        o[0] = f2bf((float)((b[v] - lap_at(G, p, v)) * invD / sr));
-        o[1] = f2bf((float)((p[v] - m) / sp));
-#pragma unroll
-        for (int c = 2; c < 16; ++c) o[c] = 0;
+        const unsigned c01 = f2bf((float)((b[v] - lap_at(G, p, v)) * invD / sr)) |
+                             ((unsigned)f2bf((float)((p[v] - m) / sp)) << 16);
+        u32x4* o = reinterpret_cast<u32x4*>(X + v * xstride);
+        o[0] = u32x4{c01, 0u, 0u, 0u};
+        if (xstride == 16) o[1] = u32x4{0u, 0u, 0u, 0u};
     }
 }
 
 // ---- convolution forward / input gradient --------------------------------------
 
-enum { OUT_BF16 = 0, OUT_F32 = 1, OUT_HEAD = 2 };
+enum { OUT_BF16 = 0, OUT_F32 = 1, OUT_HEAD = 2, OUT_POOL = 3 };
 
 // out[v][co] = act(bias[co] + sum_{tap, ci} in[nbr(v, tap)][ci] w[tap][co][ci])
 // MODE OUT_BF16: BF16 into a channel slice (ostride, ooff) with bias and
@@ -265,22 +262,40 @@ struct PlaneTile {
     static constexpr int KC = (9 * CIN + 31) / 32;  // K chunks per dz slice
     static constexpr int WBYTES = 3 * KC * 64 * 16;  // fragment-ordered weights of one output tile
     static constexpr int NCHUNK = HX * HY * CU;      // 16-byte loads per plane
-    static constexpr int PER_THREAD = (NCHUNK + 64 * WAVES - 1) / (64 * WAVES);
+};
+
+// 16-byte load slots per thread of a halo plane whose first CA channels come
+// from one source and the rest from another: each slot reads one source only
+template <int CIN, int CA, int WAVES>
+struct PlaneSlots {
+    static constexpr int T = 64 * WAVES, HXY = PlaneTile<CIN, WAVES>::HX * PlaneTile<CIN, WAVES>::HY;
+    static constexpr int NA = HXY * (CA / 8), NB = HXY * ((CIN - CA) / 8);
+    static constexpr int SA = (NA + T - 1) / T, SB = (NB + T - 1) / T, S = SA + SB;
 };
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
+// The first layer (8 input channels) and the head fit in 128 VGPRs and keep
+// four waves per SIMD (two workgroups per CU), which hide the LDS latency
+// between K chunks; there the chunks are kept apart in the schedule, so that
+// the compiler does not hoist all fragment reads.  Wider layers are limited by
+// LDS to one workgroup per CU and rely on the compiler's interleaving.
+template <int CIN, int MODE>
+constexpr int kConvMinWaves = CIN <= 8 || MODE == 2 ? 4 : 1;
+
 template <int CIN, int CA, bool UPA, int WAVES, int MODE>
-__global__ __launch_bounds__(64 * WAVES) void k_conv_march(Lvl L, SrcView A, SrcView B, const u32x4* __restrict__ wf,
+__global__ __launch_bounds__(64 * WAVES, (kConvMinWaves<CIN, MODE>)) void k_conv_march(Lvl L, SrcView A, SrcView B, const u32x4* __restrict__ wf,
                                                            const float* __restrict__ bias, void* __restrict__ out,
-                                                           int ostride, int ooff, int relu, int zchunk, int ncot)
+                                                           int ostride, int ooff, int relu, int zchunk, int ncot,
+                                                           uint16_t* __restrict__ pool, int pstride)
 {
     using PT = PlaneTile<CIN, WAVES>;
     static_assert(CIN % 8 == 0 && CA % 8 == 0 && CA <= CIN, "channel groups of 8");
-    __shared__ __align__(16) unsigned char sx[PT::PLANE];
+    __shared__ __align__(16) unsigned char sx[PT::PLANE + 16];  // plane + sink
     __shared__ u32x4 sw[PT::WBYTES / 16];
+    __shared__ float sbias[16];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int jc = lane & 15, g = lane >> 4;
@@ -288,101 +303,169 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv_march(Lvl L, SrcView A, Src
     const int z0 = (blockIdx.z / ncot) * zchunk, z1 = min(L.nz, z0 + zchunk);
     const int x0 = blockIdx.x * PT::TX, y0 = blockIdx.y * PT::TY;
 
+    // weights and bias of this output tile into LDS
     for (int e = tid; e < PT::WBYTES / 16; e += 64 * WAVES) sw[e] = wf[(long long)cot * (PT::WBYTES / 16) + e];
+    if (tid < 16) sbias[tid] = bias ? bias[16 * cot + tid] : 0.f;
 
-    // this thread's 16-byte slots of the halo plane: source, offset within a
-    // source plane, LDS offset
-    const long long planeA = (long long)A.nx * A.ny * A.stride, planeB = (long long)B.nx * B.ny * B.stride;
-    int soff[PT::PER_THREAD], loff[PT::PER_THREAD];
-    bool fromA[PT::PER_THREAD];
+    // This thread's 16-byte slots of the halo plane: SA slots over the CA / 8
+    // channel groups of A of every halo cell, then SB slots over those of B,
+    // each slot reading one source with 32-bit offsets into a buffer resource
+    // of one source plane.  Lanes past the end of a source load nothing (an
+    // offset beyond the plane) and store into a 16-byte sink behind the plane.
+    using SL = PlaneSlots<CIN, CA, WAVES>;
+    constexpr int CUA = CA / 8, CUB = PT::CU - CUA;
+    constexpr unsigned kPast = 0x80000000u;
+    const unsigned bytesA = (unsigned)A.nx * (unsigned)A.ny * (unsigned)A.stride * 2u;
+    const unsigned bytesB = (unsigned)B.nx * (unsigned)B.ny * (unsigned)B.stride * 2u;
+    unsigned soff[SL::S];
+    int loff[SL::S];
 #pragma unroll
-    for (int s = 0; s < PT::PER_THREAD; ++s) {
-        const int e = min(tid + s * 64 * WAVES, PT::NCHUNK - 1);
-        const int h = e / PT::CU, cu = e - h * PT::CU;
+    for (int s = 0; s < SL::S; ++s) {
+        const bool inA = s < SL::SA;
+        const int e = tid + (inA ? s : s - SL::SA) * SL::T;
+        const int cpc = inA ? CUA : (CUB > 0 ? CUB : 1);  // groups per cell in this source
+        const int h = e / cpc, cu = e - h * cpc;
         const int hx = h % PT::HX, hy = h / PT::HX;
         int gx = (x0 - 1 + hx) % L.nx, gy = (y0 - 1 + hy) % L.ny;
         gx = gx < 0 ? gx + L.nx : gx;
         gy = gy < 0 ? gy + L.ny : gy;
-        const int c = 8 * cu;
-        fromA[s] = c < CA;
-        if (c < CA) {
-            const int ax = UPA ? gx / 2 : gx, ay = UPA ? gy / 2 : gy;
-            soff[s] = (ay * A.nx + ax) * A.stride + A.off + c;
+        const int ax = UPA ? gx / 2 : gx, ay = UPA ? gy / 2 : gy;
+        if (inA) {
+            const bool live = e < SL::NA;
+            soff[s] = live ? (unsigned)(((ay * A.nx + ax) * A.stride + A.off + 8 * cu) * 2) : kPast;
+            loff[s] = live ? h * PT::CSTR + 16 * cu : PT::PLANE;
         } else {
-            soff[s] = (gy * B.nx + gx) * B.stride + B.off + (c - CA);
+            const bool live = e < SL::NB;
+            soff[s] = live ? (unsigned)(((gy * B.nx + gx) * B.stride + B.off + 8 * cu) * 2) : kPast;
+            loff[s] = live ? h * PT::CSTR + 16 * (CUA + cu) : PT::PLANE;
         }
-        loff[s] = h * PT::CSTR + 16 * cu;
     }
-    u32x4 pre[PT::PER_THREAD];
+    u32x4 pre[SL::S];
     auto load_plane = [&](int j) {
+        const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint16_t*>(A.p) + (long long)(UPA ? j / 2 : j) * (bytesA / 2), (short)0, (int)bytesA, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint16_t*>(B.p) + (long long)j * (bytesB / 2), (short)0, (int)bytesB, 0x00020000);
 #pragma unroll
-        for (int s = 0; s < PT::PER_THREAD; ++s) {
-            const uint16_t* src = fromA[s] ? A.p + (long long)(UPA ? j / 2 : j) * planeA + soff[s]
-                                           : B.p + (long long)j * planeB + soff[s];
-            pre[s] = *reinterpret_cast<const u32x4*>(src);
-        }
+        for (int s = 0; s < SL::S; ++s)
+            pre[s] = __builtin_amdgcn_raw_buffer_load_b128(s < SL::SA ? rA : rB, soff[s], 0, 0);
     };
     auto store_plane = [&]() {
 #pragma unroll
-        for (int s = 0; s < PT::PER_THREAD; ++s)
-            if (tid + s * 64 * WAVES < PT::NCHUNK) *reinterpret_cast<u32x4*>(sx + loff[s]) = pre[s];
+        for (int s = 0; s < SL::S; ++s) *reinterpret_cast<u32x4*>(sx + loff[s]) = pre[s];
     };
 
-    // K offsets of this lane's B fragments: chunk q, group g covers k = 32 q + 8 g
-    // .. + 7, i.e. tap9 = k / CIN (dy + 1 = tap9 / 3, dx + 1 = tap9 % 3), channels c
-    int koff[PT::KC];
+    // B fragments: chunk q, lane group g covers k = 32 q + 8 g .. + 7, i.e.
+    // tap9 = k / CIN (dy + 1 = tap9 / 3, dx + 1 = tap9 % 3), channels c.  The
+    // weights of k >= 9 CIN are zero, so those lanes read any finite operand
+    // (tap 0).  kb[q] addresses the lane's cell in the wave's first 16-cell
+    // tile; the four tiles (rows 2 wave + (n >> 1), x halves n & 1) sit at
+    // fixed distances from it.
+    int kb[PT::KC];
 #pragma unroll
     for (int q = 0; q < PT::KC; ++q) {
-        const int k = 32 * q + 8 * g;
+        const int k = 32 * q + 8 * g < 9 * CIN ? 32 * q + 8 * g : 0;
         const int tap = k / CIN, c = k - tap * CIN;
-        koff[q] = k < 9 * CIN ? ((tap / 3) * PT::HX + tap % 3) * PT::CSTR + 2 * c : -1;
+        kb[q] = ((2 * wave + tap / 3) * PT::HX + jc + tap % 3) * PT::CSTR + 2 * c;
     }
-    // this wave's four 16-cell tiles: rows 2 wave + (n >> 1), x halves n & 1
-    int cbase[4];
-#pragma unroll
-    for (int n = 0; n < 4; ++n) cbase[n] = ((2 * wave + (n >> 1)) * PT::HX + 16 * (n & 1) + jc) * PT::CSTR;
+    constexpr int kTileOff[4] = {0, 16 * PT::CSTR, PT::HX * PT::CSTR, (PT::HX + 16) * PT::CSTR};
 
-    float bv[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bv[r] = bias ? bias[16 * cot + 4 * g + r] : 0.f;
-
-    // acc[0]: output plane j + 1 (dz = -1), acc[1]: plane j, acc[2]: plane j - 1
+    // Output plane t accumulates in acc[(t - z0 + 1) mod 3]; the z loop is
+    // unrolled by three so that the slots are static.
     floatx4 acc[3][4];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[d][n] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    auto store_out = [&](int z) {
+    // Output plane z through a buffer resource: lanes outside the grid (and,
+    // for the head, lanes of channels other than 0) get an offset beyond the
+    // plane, which the buffer range check drops.  No branch, so the wait for
+    // the next plane's loads does not also wait for these stores.
+    //
+    // OUT_POOL also writes the 2 x 2 x 2 mean of the stored (BF16) output at
+    // half resolution into pool (pstride channels, this tile's 16 from
+    // 16 cot), summed in the order x, then y, then z fastest-first: the
+    // x pair sits in lanes jc, jc + 1, the y pair in tiles n, n + 2 of the
+    // same lane, and the z pair in consecutive planes, carried in psum.
+    constexpr unsigned ESZ = MODE == OUT_HEAD ? 4u : 2u;
+    const unsigned pbytes = (unsigned)L.nx * (unsigned)L.ny * (unsigned)ostride * ESZ;
+    const unsigned qbytes = (unsigned)(L.nx / 2) * (unsigned)(L.ny / 2) * (unsigned)pstride * 2u;
+    float psum[2][4] = {};
+    float bv[4];  // from LDS once the weights are staged
+    auto store_out = [&](int z, const floatx4* o, bool live) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            static_cast<char*>(out) + (long long)max(z, 0) * pbytes, (short)0, (int)pbytes, 0x00020000);
+        unsigned h[4][2];
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             const int x = x0 + 16 * (n & 1) + jc, y = y0 + 2 * wave + (n >> 1);
-            if (x >= L.nx || y >= L.ny) continue;
-            const long long v = ((long long)z * L.ny + y) * L.nx + x;
-            if (MODE == OUT_BF16) {
-                unsigned h[4];
+            const bool in = live && x < L.nx && y < L.ny;
+            const unsigned v = (unsigned)y * (unsigned)L.nx + (unsigned)x;
+            if (MODE == OUT_HEAD) {  // channel 0 only
+                const unsigned off = in && g == 0 ? v * ESZ : 0x80000000u;
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, o[n][0] + bv[0]), r, off, 0, 0);
+            } else {
+                float val[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float val = acc[2][n][r] + bv[r];
-                    if (relu) val = fmaxf(val, 0.f);
-                    h[r] = f2bf(val);
+                for (int q = 0; q < 4; ++q) val[q] = relu ? fmaxf(o[n][q] + bv[q], 0.f) : o[n][q] + bv[q];
+                h[n][0] = f2bf(val[0]) | ((unsigned)f2bf(val[1]) << 16);
+                h[n][1] = f2bf(val[2]) | ((unsigned)f2bf(val[3]) << 16);
+                const unsigned off = in ? (v * ostride + ooff + 16 * cot + 4 * g) * ESZ : 0x80000000u;
+                __builtin_amdgcn_raw_buffer_store_b64(u32x2{h[n][0], h[n][1]}, r, off, 0, 0);
+            }
+        }
+        if (MODE == OUT_POOL) {
+            const bool odd = z & 1;
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const unsigned sh = 16 * (q & 1);
+                    const float f0 = __uint_as_float((h[m][q >> 1] >> sh) << 16);
+                    const float f2 = __uint_as_float((h[m + 2][q >> 1] >> sh) << 16);
+                    // quad_perm [1, 1, 3, 3]: the even lane of each pair gets its odd neighbour
+                    const float f0n = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, f0), 0xF5, 0xf, 0xf, false));
+                    const float f2n = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, f2), 0xF5, 0xf, 0xf, false));
+                    float a = odd ? psum[m][q] : 0.f;
+                    a += f0;
+                    a += f0n;
+                    a += f2;
+                    a += f2n;
+                    psum[m][q] = a;
                 }
-                *reinterpret_cast<u32x2*>(static_cast<uint16_t*>(out) + v * ostride + ooff + 16 * cot + 4 * g) =
-                    u32x2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
-            } else if (g == 0) {  // OUT_HEAD: channel 0 only
-                static_cast<float*>(out)[v] = acc[2][n][0] + bv[0];
+            {  // written on odd planes only, but issued on every plane (see above)
+                const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+                    pool + (long long)max(z >> 1, 0) * (qbytes / 2), (short)0, (int)qbytes, 0x00020000);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const int x = x0 + 16 * m + jc, y = y0 + 2 * wave;
+                    const bool in = live && odd && x < L.nx && y < L.ny && (jc & 1) == 0;
+                    const unsigned v = (unsigned)(y >> 1) * (unsigned)(L.nx >> 1) + (unsigned)(x >> 1);
+                    const unsigned off = in ? (v * pstride + 16 * cot + 4 * g) * 2u : 0x80000000u;
+                    __builtin_amdgcn_raw_buffer_store_b64(
+                        u32x2{f2bf(psum[m][0] * 0.125f) | ((unsigned)f2bf(psum[m][1] * 0.125f) << 16),
+                              f2bf(psum[m][2] * 0.125f) | ((unsigned)f2bf(psum[m][3] * 0.125f) << 16)},
+                        rq, off, 0, 0);
+                }
             }
         }
     };
 
-    __syncthreads();  // weights in LDS
-    int j = z0 - 1;
-    if (j >= 0) {
-        load_plane(j);
+    __syncthreads();  // weights and bias in LDS
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bv[r] = sbias[4 * g + r];
+    if (z0 - 1 >= 0) {
+        load_plane(z0 - 1);
         store_plane();
     }
     __syncthreads();
-    for (; j <= z1; ++j) {
+    // step with input plane j (in LDS), U = (j - z0 + 1) mod 3: the dz slices
+    // d = 0, 1, 2 add to output planes j + 1, j, j - 1; plane j - 1 is then
+    // complete, stored, and its slot cleared for plane j + 2
+    auto step = [&](const int j, auto U) {
+        constexpr int u = decltype(U)::value;
+        constexpr int slot[3] = {(u + 1) % 3, u, (u + 2) % 3};
         const bool next = j + 1 <= z1 && j + 1 < L.nz;  // uniform
         if (next) load_plane(j + 1);
         if (j >= 0 && j < L.nz) {
@@ -390,45 +473,62 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv_march(Lvl L, SrcView A, Src
             for (int q = 0; q < PT::KC; ++q) {
                 bf16x8 bx[4];
 #pragma unroll
-                for (int n = 0; n < 4; ++n) {
-                    u32x4 raw = u32x4{0u, 0u, 0u, 0u};
-                    if (koff[q] >= 0) raw = *reinterpret_cast<const u32x4*>(sx + cbase[n] + koff[q]);
-                    bx[n] = __builtin_bit_cast(bf16x8, raw);
-                }
+                for (int n = 0; n < 4; ++n)
+                    bx[n] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(sx + kb[q] + kTileOff[n]));
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     const bf16x8 aw = __builtin_bit_cast(bf16x8, sw[(d * PT::KC + q) * 64 + lane]);
 #pragma unroll
-                    for (int n = 0; n < 4; ++n) acc[d][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[n], acc[d][n], 0, 0, 0);
+                    for (int n = 0; n < 4; ++n)
+                        acc[slot[d]][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[n], acc[slot[d]][n], 0, 0, 0);
                 }
+                if (kConvMinWaves<CIN, MODE> > 1) __builtin_amdgcn_sched_barrier(0);
             }
         }
-        if (j - 1 >= z0) store_out(j - 1);
+        // unconditional, so that the stores are the same on every path and
+        // the wait for the next plane's loads need not cover them
+        store_out(j - 1, acc[slot[2]], j - 1 >= z0);
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            acc[2][n] = acc[1][n];
-            acc[1][n] = acc[0][n];
-            acc[0][n] = floatx4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int n = 0; n < 4; ++n) acc[slot[2]][n] = floatx4{0.f, 0.f, 0.f, 0.f};
         __syncthreads();  // all reads of plane j done
         if (next) store_plane();
         __syncthreads();
+    };
+    for (int j = z0 - 1; j <= z1; j += 3) {
+        step(j, std::integral_constant<int, 0>{});
+        if (j + 1 > z1) break;
+        step(j + 1, std::integral_constant<int, 1>{});
+        if (j + 2 > z1) break;
+        step(j + 2, std::integral_constant<int, 2>{});
     }
 }
 
 template <int CIN, int CA, bool UPA, int WAVES, int MODE>
 hipError_t conv_march(const Lvl& L, const SrcView& A, const SrcView& B, const uint16_t* wf, int ncot,
-                      const float* bias, void* out, int ostride, int ooff, int relu, hipStream_t s)
+                      const float* bias, void* out, int ostride, int ooff, int relu, hipStream_t s,
+                      uint16_t* pool = nullptr, int pstride = 0)
 {
     using PT = PlaneTile<CIN, WAVES>;
+    // planes of the output and of both sources stay below 2^31 bytes (32-bit
+    // buffer offsets, with 2^31 as the out-of-range marker)
+    if ((long long)L.nx * L.ny * ostride * (MODE == OUT_BF16 ? 2 : 4) >= (1ll << 31) ||
+        (long long)A.nx * A.ny * A.stride * 2 >= (1ll << 31) || (long long)B.nx * B.ny * B.stride * 2 >= (1ll << 31))
+        return hipErrorInvalidValue;
     const int tx = (L.nx + PT::TX - 1) / PT::TX, ty = (L.ny + PT::TY - 1) / PT::TY;
     // z chunks: about 2048 workgroups, at least 8 output planes each
     const long long tiles = (long long)tx * ty * ncot;
     int nzc = (int)std::max<long long>(1, std::min<long long>(L.nz / 8, (2048 + tiles - 1) / tiles));
-    const int zchunk = (L.nz + nzc - 1) / nzc;
+    int zchunk = (L.nz + nzc - 1) / nzc;
+    if (MODE == OUT_POOL) {  // whole z pairs per workgroup, even extents
+        if (L.nx % 2 || L.ny % 2 || L.nz % 2 || pool == nullptr || pstride < 16 * ncot ||
+            (long long)(L.nx / 2) * (L.ny / 2) * pstride * 2 >= (1ll << 31))
+            return hipErrorInvalidValue;
+        zchunk += zchunk & 1;
+    }
     nzc = (L.nz + zchunk - 1) / zchunk;
     hipLaunchKernelGGL((k_conv_march<CIN, CA, UPA, WAVES, MODE>), dim3(tx, ty, nzc * ncot), dim3(64 * WAVES), 0, s, L, A,
-                       B, reinterpret_cast<const u32x4*>(wf), bias, out, ostride, ooff, relu, zchunk, ncot);
+                       B, reinterpret_cast<const u32x4*>(wf), bias, out, ostride, ooff, relu, zchunk, ncot, pool,
+                       pstride);
     return hipGetLastError();
 }
 
@@ -584,26 +684,6 @@ __global__ void k_bgrad_reduce(const float* __restrict__ part, int nblk, int C, 
 }
 
 // ---- pooling, upsampling, concatenation and their adjoints ---------------------------
-
-// dst[v'][c] = bf16(mean of the 8 fine cells' src[child * sstride + soff + c]); Lc: coarse level
-__global__ void k_pool(Lvl Lc, const uint16_t* __restrict__ src, int sstride, int soff, int C, uint16_t* __restrict__ dst)
-{
-    const long long total = Lc.n * C;
-    const int fnx = 2 * Lc.nx, fny = 2 * Lc.ny;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
-        const long long v = e / C;
-        const int c = (int)(e % C);
-        int x, y, z;
-        cell_xyz(Lc, v, x, y, z);
-        float a = 0.f;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const long long f = ((long long)(2 * z + (q >> 2)) * fny + (2 * y + ((q >> 1) & 1))) * fnx + (2 * x + (q & 1));
-            a += bf2f(src[f * sstride + soff + c]);
-        }
-        dst[v * C + c] = f2bf(a * 0.125f);
-    }
-}
 
 // dst[v][doff + c] (stride dstride) = src[parent(v)][c]; Lf: fine level
 __global__ void k_up(Lvl Lf, const uint16_t* __restrict__ src, int C, uint16_t* __restrict__ dst, int dstride, int doff)
@@ -971,7 +1051,7 @@ hipError_t NetModel::normalise(const double* b, const double* p_prev)
     hipLaunchKernelGGL(k_mean_from, dim3(1), dim3(256), 0, s_, red_, n, sc_);
     hipLaunchKernelGGL(k_sumsq_pr, dim3(kRedBlocks), dim3(256), 0, s_, G, p_prev, b, n, 1.0 / D_, sc_, red_);
     hipLaunchKernelGGL(k_scale_from, dim3(1), dim3(256), 0, s_, red_, n, sc_);
-    hipLaunchKernelGGL(k_normalise, dim3(g1(n)), dim3(256), 0, s_, G, b, p_prev, n, 1.0 / D_, sc_, X_);
+    hipLaunchKernelGGL(k_normalise, dim3(g1(n)), dim3(256), 0, s_, G, b, p_prev, n, 1.0 / D_, sc_, X_, xstride());
     return hipGetLastError();
 }
 
@@ -989,16 +1069,18 @@ hipError_t NetModel::forward()
         return SrcView{p, stride, off, nx_[lvl], ny_[lvl], nz_[lvl]};
     };
     const SrcView none{};
-    // e1 = relu(conv1(x)) into channels 32..47 of C1
-    NCHK((conv_march<8, 8, false, 8, OUT_BF16>(l0, view(X_, 16, 0, 0), none, Wf_ + wf_off_[0], 1, P + L_[0].b_off,
-                                                 C1_, 48, 32, 1, s_)));
-    hipLaunchKernelGGL(k_pool, dim3(g1(l1.n * 16)), dim3(256), 0, s_, l1, C1_, 48, 32, 16, Q1_);
-    NCHK(hipGetLastError());
-    // e2 = relu(conv2(pool e1)) into channels 64..95 of C2
-    NCHK((conv_march<16, 16, false, 8, OUT_BF16>(l1, view(Q1_, 16, 0, 1), none, Wf_ + wf_off_[1], 2, P + L_[1].b_off,
-                                                   C2_, 96, 64, 1, s_)));
-    hipLaunchKernelGGL(k_pool, dim3(g1(l2.n * 32)), dim3(256), 0, s_, l2, C2_, 96, 64, 32, Q2_);
-    NCHK(hipGetLastError());
+    // Training keeps the skip tensors e1, e2 inside the concatenated inputs of
+    // conv5 and conv4 (C1 = [up d2 | e1], C2 = [up e3 | e2]) for the weight
+    // gradients; inference stores them densely, so that their rows are whole
+    // cache lines.
+    const int c1s = training_ ? 48 : 16, c1o = training_ ? 32 : 0;
+    const int c2s = training_ ? 96 : 32, c2o = training_ ? 64 : 0;
+    // e1 = relu(conv1(x)) and its 2 x 2 x 2 mean into Q1
+    NCHK((conv_march<8, 8, false, 8, OUT_POOL>(l0, view(X_, xstride(), 0, 0), none, Wf_ + wf_off_[0], 1,
+                                                 P + L_[0].b_off, C1_, c1s, c1o, 1, s_, Q1_, 16)));
+    // e2 = relu(conv2(pool e1)) and its mean into Q2
+    NCHK((conv_march<16, 16, false, 8, OUT_POOL>(l1, view(Q1_, 16, 0, 1), none, Wf_ + wf_off_[1], 2, P + L_[1].b_off,
+                                                   C2_, c2s, c2o, 1, s_, Q2_, 32)));
     // e3 = relu(conv3(pool e2))
     NCHK((conv_march<32, 32, false, 8, OUT_BF16>(l2, view(Q2_, 32, 0, 2), none, Wf_ + wf_off_[2], 4, P + L_[2].b_off,
                                                    E3_, 64, 0, 1, s_)));
@@ -1008,14 +1090,14 @@ hipError_t NetModel::forward()
         hipLaunchKernelGGL(k_up, dim3(g1(l1.n * 64)), dim3(256), 0, s_, l1, E3_, 64, C2_, 96, 0);
         NCHK(hipGetLastError());
     }
-    NCHK((conv_march<96, 64, true, 4, OUT_BF16>(l1, view(E3_, 64, 0, 2), view(C2_, 96, 64, 1), Wf_ + wf_off_[3], 2,
+    NCHK((conv_march<96, 64, true, 4, OUT_BF16>(l1, view(E3_, 64, 0, 2), view(C2_, c2s, c2o, 1), Wf_ + wf_off_[3], 2,
                                                   P + L_[3].b_off, D2_, 32, 0, 1, s_)));
     // d1 = relu(conv5([up d2, e1]))
     if (training_) {
         hipLaunchKernelGGL(k_up, dim3(g1(l0.n * 32)), dim3(256), 0, s_, l0, D2_, 32, C1_, 48, 0);
         NCHK(hipGetLastError());
     }
-    NCHK((conv_march<48, 32, true, 8, OUT_BF16>(l0, view(D2_, 32, 0, 1), view(C1_, 48, 32, 0), Wf_ + wf_off_[4], 1,
+    NCHK((conv_march<48, 32, true, 8, OUT_BF16>(l0, view(D2_, 32, 0, 1), view(C1_, c1s, c1o, 0), Wf_ + wf_off_[4], 1,
                                                   P + L_[4].b_off, D1_, 16, 0, 1, s_)));
     // y = conv6(d1)
     NCHK((conv_march<16, 16, false, 8, OUT_HEAD>(l0, view(D1_, 16, 0, 0), none, Wf_ + wf_off_[5], 1, P + L_[5].b_off,

@@ -99,11 +99,20 @@ struct PlaneCoef {
 template <typename T>
 __device__ __forceinline__ PlaneCoef<T> plane_coef(const Coef<T>& k, int q, int nz)
 {
-    // values, not references, in the selects: a select between two fields'
-    // addresses would keep the coefficients in memory
-    const T k0 = k.k0, k0w = k.k0w, k0ww = k.k0ww, kz = k.kz;
+    // The selects act on the bit patterns: integer selects of uniform values
+    // stay in scalar registers (floating-point ones become per-lane
+    // v_cndmask), and values rather than references avoid selecting between
+    // two fields' addresses, which would keep the coefficients in memory.
+    using U = std::conditional_t<sizeof(T) == 4, unsigned, unsigned long long>;
+    const U k0 = __builtin_bit_cast(U, k.k0), k0w = __builtin_bit_cast(U, k.k0w), k0ww = __builtin_bit_cast(U, k.k0ww),
+            kz = __builtin_bit_cast(U, k.kz);
     const bool top = q == nz - 1, bottom = q == 0;
-    return PlaneCoef<T>{top && bottom ? k0ww : (top || bottom ? k0w : k0), top ? T(0) : kz, bottom ? T(0) : kz};
+    // centre coefficient by the number of walls (0, 1, 2) with masks
+    const int walls = (int)top + (int)bottom;
+    const U m0 = (U)(long long)((walls - 1) >> 31), m2 = (U)(long long)(-(walls >> 1));
+    const U c0 = (k0 & m0) | (k0w & ~(m0 | m2)) | (k0ww & m2);
+    return PlaneCoef<T>{__builtin_bit_cast(T, c0), __builtin_bit_cast(T, top ? U(0) : kz),
+                        __builtin_bit_cast(T, bottom ? U(0) : kz)};
 }
 
 template <typename T>
@@ -211,7 +220,12 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
     const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
     constexpr int PTS = kTileY / WAVES;  // rows per thread
     constexpr int OX = kTileX - 2 * NT, OY = kRows - 2 * NT;
-    __shared__ T lds[2][NT][kRows][kTileX];  // step t reads buffer (t-1) & 1, writes t & 1
+    // LDS holds, per stage, only the rows read across wavefronts: slot 2w + 1
+    // is wavefront w's first row, 2w + 2 its last, 0 and 2 WAVES + 1 the halo
+    // rows 0 and kRows - 1.  Wavefront w then reads the row above its first
+    // from slot 2w and the row below its last from slot 2w + 3.
+    constexpr int kSlots = 2 * WAVES + 2;
+    __shared__ T lds[2][NT][kSlots][kTileX];  // step t reads buffer (t-1) & 1, writes t & 1
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -244,17 +258,20 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
 #pragma unroll
     for (int s = 0; s < NT; ++s) c[s] = coef_of<T>(kc, s);
 
-    // The march is unrolled by kUnroll = 6 steps so that every register slot
-    // is fixed at compile time and no value moves between registers: stage s
-    // keeps its last three planes in V[s][(q - t_begin) mod 3] and b of the
-    // last six planes sits in Bz[(q - t_begin) mod 6].  Plane t + 1 of p and
-    // b is requested while plane t is processed (p into Pn, b straight into
-    // its slot), so a step of loads is in flight across the barriers.  Loads
-    // past the top wall are clamped to plane nz - 1; ring slots of planes -1
-    // and nz hold finite stale values that the wall coefficients zero out.
-    constexpr int kUnroll = 6;
+    // The march is unrolled by kUnroll steps so that every register slot is
+    // fixed at compile time and no value moves between registers: stage s
+    // keeps its last three planes in V[s][(q - t_begin) mod 3], b of the last
+    // kRing planes sits in Bz[(q - t_begin) mod kRing], and the LDS buffers
+    // alternate with the step's parity.  Plane t + 1 of p and b is requested
+    // while plane t is processed (p into Pn, b straight into its slot, which
+    // therefore must not hold plane t - NT, still read by the last stage:
+    // kRing >= NT + 2, a multiple of 3).  Loads past the top wall are clamped
+    // to plane nz - 1; ring slots of planes -1 and nz hold finite stale values
+    // that the wall coefficients zero out.
+    constexpr int kRing = (NT + 2 + 2) / 3 * 3;
+    constexpr int kUnroll = kRing % 2 == 0 ? kRing : 2 * kRing;
     T V[NT][3][PTS];
-    T Bz[kUnroll][PTS];
+    T Bz[kRing][PTS];
     T Pn[PTS];
 #pragma unroll
     for (int s = 0; s < NT; ++s)
@@ -263,7 +280,7 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
 #pragma unroll
             for (int m = 0; m < PTS; ++m) V[s][k][m] = T(0);
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k)
+    for (int k = 0; k < kRing; ++k)
 #pragma unroll
         for (int m = 0; m < PTS; ++m) Bz[k][m] = T(0);
 
@@ -288,7 +305,7 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
         constexpr int u = decltype(U)::value;
         // slot of plane t - k in the stage rings and in the b ring
         auto vs = [](int k) { return ((u - k) % 3 + 3) % 3; };
-        auto bs = [](int k) { return ((u - k) % kUnroll + kUnroll) % kUnroll; };
+        auto bs = [](int k) { return ((u - k) % kRing + kRing) % kRing; };
         if (t > t_end) return;
         auto& rd = lds[(u + 1) & 1];  // planes written by the previous step
         auto& wr = lds[u & 1];
@@ -321,14 +338,13 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
             T res[PTS];
 #pragma unroll
             for (int m = 0; m < PTS; ++m) {
-                const int r = row[m];
                 // x neighbours: the centre register of the neighbouring lanes
                 const T pcm = V[s - 1][vs(s)][m];
                 // y neighbours: this thread's adjacent rows, or (at the
                 // wavefront's first and last row) the neighbouring wavefront's
                 // row through LDS
-                const T ps = m > 0 ? V[s - 1][vs(s)][m > 0 ? m - 1 : 0] : rd[s - 1][r - 1][lane];
-                const T pn = m + 1 < PTS ? V[s - 1][vs(s)][m + 1 < PTS ? m + 1 : 0] : rd[s - 1][r + 1][lane];
+                const T ps = m > 0 ? V[s - 1][vs(s)][m > 0 ? m - 1 : 0] : rd[s - 1][2 * wave][lane];
+                const T pn = m + 1 < PTS ? V[s - 1][vs(s)][m + 1 < PTS ? m + 1 : 0] : rd[s - 1][2 * wave + 3][lane];
                 res[m] = sweep_point<T>(c[s - 1], kq, lane_from_below(pcm), lane_from_above(pcm), ps, pn,
                                         V[s - 1][vs(s - 1)][m], V[s - 1][vs(s + 1)][m], pcm, Bz[bs(s)][m]);
                 if (s < NT) V[s][vs(s)][m] = res[m];
@@ -346,8 +362,11 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
         for (int s = 0; s < NT; ++s)
 #pragma unroll
             for (int m = 0; m < PTS; ++m)
-                if (m == 0 || m == PTS - 1) wr[s][row[m]][lane] = V[s][vs(s)][m];  // rows other wavefronts read
-        if (hrow >= 0) wr[0][hrow][lane] = Vh;
+            {  // rows other wavefronts read
+                if (m == 0) wr[s][2 * wave + 1][lane] = V[s][vs(s)][m];
+                if (m == PTS - 1) wr[s][2 * wave + 2][lane] = V[s][vs(s)][m];
+            }
+        if (hrow >= 0) wr[0][hrow == 0 ? 0 : kSlots - 1][lane] = Vh;
         __syncthreads();  // one barrier: double-buffered planes
     };
 
@@ -444,8 +463,14 @@ hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wt
                            stage_coefs<T>(g, wts, 1));
         return hipGetLastError();
     }
-    if (nfused == 2) return launch_fused<T, 2, kWaves<T>>(g, b, p, out, wts, s);
-    if (nfused == 4) return launch_fused<T, 4, kWaves<T>>(g, b, p, out, wts, s);
+    switch (nfused) {
+    case 2: return launch_fused<T, 2, kWaves<T>>(g, b, p, out, wts, s);
+    case 3: return launch_fused<T, 3, kWaves<T>>(g, b, p, out, wts, s);
+    case 4: return launch_fused<T, 4, kWaves<T>>(g, b, p, out, wts, s);
+    }
+    if constexpr (sizeof(T) == 4) {  // FP64 rings do not fit deeper pipelines in registers
+        if (nfused == 5) return launch_fused<T, 5, kWaves<T>>(g, b, p, out, wts, s);
+    }
     return hipErrorInvalidValue;
 }
 template hipError_t relax<double>(const Geo&, const double*, const double*, double*, const Weights&, int, hipStream_t);

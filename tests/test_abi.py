@@ -58,7 +58,7 @@ def test_workspace_bytes_valid_and_invalid():
     assert big > n_ok
     for bad in (dict(nz=1), dict(nx=0), dict(nu=0.0), dict(dt=-1.0), dict(lx=float("nan")),
                 dict(precision=7), dict(poisson_maxit=0), dict(poisson_rtol=-1.0), dict(srj_reduction=1.5),
-                dict(les=2), dict(tblock=3), dict(tblock=8), dict(cn_tol=2.0), dict(srj_m=4)):
+                dict(les=2), dict(tblock=-1), dict(tblock=6), dict(cn_tol=2.0), dict(srj_m=4)):
         assert lib.stp_workspace_bytes(ctypes.byref(cfg(**bad))) == 0, bad
     assert lib.stp_workspace_bytes(None) == 0
 

@@ -209,17 +209,19 @@ def test_full_size_sweep_sampled(gpu, dtype):
 
 @pytest.mark.parametrize("g", [(70, 45, 33, 2.0, 1.5, 1.0), (130, 64, 40, 4.0, 2.0, 2.0), (64, 32, 5, 1.0, 1.0, 1.0)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("nt", [2, 4])
+@pytest.mark.parametrize("nt", [2, 3, 4, 5])
 def test_fused_sweeps_equal_single_sweeps_bitwise(gpu, g, dtype, nt):
     """NT sweeps fused into one launch (LDS tile, z-march) reproduce NT single
-    sweeps bit for bit, including ragged tiles, the periodic seams and the walls."""
+    sweeps bit for bit, including ragged tiles, the periodic seams and the
+    walls; 2 NT + 1 sweeps also run a shorter remainder launch (FP64 fuses at
+    most 4)."""
     import torch
     print(f"fused grid={g} dtype={dtype} nt={nt}", flush=True)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     r = inputs.rng(19)
     p = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
     b = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
-    om = [1.3, 57.0, 0.6, 3.1, 11.0, 0.9, 2.2, 40.0][: 2 * nt]
+    om = [1.3, 57.0, 0.6, 3.1, 11.0, 0.9, 2.2, 40.0, 0.7, 5.5, 1.9, 23.0, 1.1][: 2 * nt + 1]
     ch1 = channel(g, tblock=1)
     chf = channel(g, tblock=nt)
     p1 = p.clone()
@@ -230,23 +232,23 @@ def test_fused_sweeps_equal_single_sweeps_bitwise(gpu, g, dtype, nt):
     assert torch.equal(p1, pf)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_fused_sweeps_full_size_bitwise(gpu, dtype):
-    """The 4-sweep launch at the benchmark grid (512x256x192, the launch
+@pytest.mark.parametrize("dtype,nt", [("f32", 4), ("f32", 5), ("f64", 4)])
+def test_fused_sweeps_full_size_bitwise(gpu, dtype, nt):
+    """The fused launch at the benchmark grid (512x256x192, the launch
     configuration the bench times: several z-chunks per tile column, ragged
-    last tiles in x and y) equals four single sweeps bit for bit; single sweeps
-    at this size are checked against the oracle in test_full_size_sweep_sampled."""
+    last tiles in x and y) equals single sweeps bit for bit; single sweeps at
+    this size are checked against the oracle in test_full_size_sweep_sampled."""
     import torch
     g = (512, 256, 192, 4 * math.pi, 2 * math.pi, 2.0)
-    print(f"fused full size dtype={dtype}", flush=True)
+    print(f"fused full size dtype={dtype} nt={nt}", flush=True)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     r = inputs.rng(23)
     p = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
     b = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
-    om = [1.3, 57.0, 0.6, 3.1, 11.0, 0.9, 2.2, 40.0]
+    om = [1.3, 57.0, 0.6, 3.1, 11.0, 0.9, 2.2, 40.0, 0.7, 5.5, 1.9, 23.0][: 2 * nt]
     p1, pf = p.clone(), p.clone()
     channel(g, tblock=1).relax(b, p1, om)
-    channel(g, tblock=4).relax(b, pf, om)
+    channel(g, tblock=nt).relax(b, pf, om)
     torch.cuda.synchronize()
     assert torch.equal(p1, pf)
 
