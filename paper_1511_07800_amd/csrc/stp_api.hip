@@ -174,6 +174,18 @@ int chebyshev_degree(double a, double b, double reduction)
     return std::max(1, (int)std::ceil(std::acosh(1.0 / reduction) / std::acosh(s)));
 }
 
+// max of a[0..n): four independent running maxima (a max does not depend on
+// the order), so the compare chain does not serialise the scan
+static double max_of(const double* a, int n)
+{
+    double t[4] = {-1e300, -1e300, -1e300, -1e300};
+    int k = 0;
+    for (; k + 4 <= n; k += 4)
+        for (int q = 0; q < 4; ++q) t[q] = a[k + q] > t[q] ? a[k + q] : t[q];
+    for (; k < n; ++k) t[0] = a[k] > t[0] ? a[k] : t[0];
+    return std::max(std::max(t[0], t[1]), std::max(t[2], t[3]));
+}
+
 std::vector<double> chebyshev_leja_nodes(double a, double b, int m)
 {
     std::vector<double> x(m);
@@ -183,7 +195,14 @@ std::vector<double> chebyshev_leja_nodes(double a, double b, int m)
     // a relative 1e-9 of the best count as tied (the nodes are symmetric, so
     // exact ties occur and round-off must not decide them); ties go to the
     // lower index.
-    std::vector<char> used(m, 0);
+    // The logs come from a table: with theta_i = pi (2i + 1) / (2m) and
+    // h = (b - a) / 2, x_i - x_j = -2h sin(pi (i + j + 1) / (2m)) sin(pi (i - j) / (2m)),
+    // so log|x_i - x_j| = log(2h) + T[i + j + 1] + T[|i - j|] with
+    // T[n] = log sin(pi n / (2m)), 0 < n < 2m: 2m logs instead of m^2 / 2.
+    const double l2h = std::log(b - a);
+    std::vector<double> T(2 * m + 1, 0.0);  // T[0], T[2m] are never read
+    for (int n = 1; n < 2 * m; ++n) T[n] = std::log(std::sin(M_PI * n / (2.0 * m)));
+    constexpr double kPlaced = -1e300;  // finite, below any sum of logs
     std::vector<double> logd(m, 0.0);
     std::vector<double> out;
     out.reserve(m);
@@ -191,19 +210,18 @@ std::vector<double> chebyshev_leja_nodes(double a, double b, int m)
     for (int k = 1; k < m; ++k)
         if (std::fabs(x[k]) > std::fabs(x[cur])) cur = k;
     for (int t = 0; t < m; ++t) {
-        used[cur] = 1;
+        logd[cur] = kPlaced;
         out.push_back(1.0 / x[cur]);
         if (t == m - 1) break;
-        double top = -INFINITY;
-        for (int k = 0; k < m; ++k) {
-            if (used[k]) continue;
-            logd[k] += std::log(std::fabs(x[k] - x[cur]));
-            top = std::max(top, logd[k]);
-        }
+        double* L = logd.data();
+        const double* Tp = T.data() + cur + 1;  // T[k + cur + 1]
+        const double* Tm = T.data() + cur;      // T[cur - k] = Tm[-k]
+        for (int k = 0; k < cur; ++k) L[k] += (l2h + Tp[k]) + Tm[-k];
+        for (int k = cur + 1; k < m; ++k) L[k] += (l2h + Tp[k]) + T[k - cur];
+        const double top = max_of(L, m);
         const double tol = 1e-9 * std::max(1.0, std::fabs(top));
-        int best = -1;
-        for (int k = 0; k < m && best < 0; ++k)
-            if (!used[k] && logd[k] >= top - tol) best = k;
+        int best = 0;
+        while (!(L[best] >= top - tol)) ++best;
         cur = best;
     }
     return out;
