@@ -9,8 +9,10 @@ value  = relaxation cell-updates per second over the whole timed steps
          (sweeps x cells / wall time of the steps, everything included).
 Also reported: LES steps/s for the mixed (FP32 sweeps, FP64 residual and
 defect correction) and plain FP64 solves at the same relative residual, the
-dominant kernel's roofline (FP32 relaxation sweep, HBM-bound), and the FP64
-oracle's sweep rate on the host cores.
+fields of every variant against the FP64 run's after the same steps, the
+dominant kernel's roofline (FP32 relaxation sweep, HBM-bound), a table of
+back-to-back sweep rates for every fusion depth in FP32 and FP64 beside a
+plain device copy, and the FP64 oracle's sweep rate on the host cores.
 """
 import argparse
 import json
@@ -37,6 +39,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start run")
+    ap.add_argument("--no-table", action="store_true", help="skip the sweep-rate table")
     ap.add_argument("--fixed-cycles", action="store_true", help="repeat the fixed 1e-3 SRJ cycle (no adaptive sizing)")
     ap.add_argument("--sweeps", type=int, default=200, help="sweeps in the kernel roofline timing")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -142,6 +145,67 @@ def profile_kernels(wl):
     print("profile-kernels done", flush=True)
 
 
+def relax_sweep_table(wl, timed=1020, warm=60):
+    """Back-to-back sweeps of the built-in SRJ cycle from p = 0 on the
+    workload's grid (b ~ U(-1, 1) minus its mean), for every fusion depth:
+    `warm` untimed sweeps, then `timed` sweeps between events on the stream
+    the library runs on (both divisible by 1..5, so every launch fuses the
+    full depth).  compulsory_GBs counts 3 words per cell per launch,
+    effective_GBs 3 words per cell per sweep.  copy_GBs: a plain device copy
+    of 256 MiB (read + write), the practical streaming ceiling."""
+    import torch
+    from paper_1511_07800_amd import Channel, inputs
+    nx, ny, nz = wl["nx"], wl["ny"], wl["nz"]
+    n = nx * ny * nz
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    e0.record()
+    for _ in range(20):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    out = {"copy_GBs": round(20 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)}
+    del a, c
+    b64 = torch.from_numpy(inputs.poisson_rhs(nx, ny, nz, seed=1511)).cuda()
+    for name, tdt, word, depths in (("f32", torch.float32, 4, (1, 2, 3, 4, 5)), ("f64", torch.float64, 8, (1, 2, 3, 4))):
+        b = b64.to(tdt)
+        rows = {}
+        for tb in depths:
+            ch = Channel(nx, ny, nz, wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"], dt=wl["dt"],
+                         tblock=tb)
+            om = ch.schedule()
+            seq = [om[k % len(om)] for k in range(warm + timed)]
+            p = torch.zeros_like(b)
+            ch.relax(b, p, seq[:warm])
+            e0.record()
+            ch.relax(b, p, seq[warm:])
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3
+            rows[str(tb)] = {"us_per_sweep": round(1e6 * sec / timed, 2),
+                             "gcell_updates_per_s": round(n * timed / sec / 1e9, 1),
+                             "compulsory_GBs": round(3 * word * n * (timed / tb) / sec / 1e9, 1),
+                             "effective_GBs": round(3 * word * n * timed / sec / 1e9, 1)}
+            ch.close()
+            del ch, p
+            torch.cuda.empty_cache()
+        out[name] = rows
+    return out
+
+
+def fields_of(ch):
+    from paper_1511_07800_amd import STP_U, STP_V, STP_W, STP_P
+    return [ch.field(k).clone() for k in (STP_U, STP_V, STP_W, STP_P)]
+
+
+def field_errors(got, ref):
+    """Relative L2 difference of u, v, w, p against the reference fields."""
+    return {name: float((g - r).norm() / r.norm()) for name, g, r in zip("uvwp", got, ref)}
+
+
 def cpu_baseline(wl, seconds=12.0):
     """The FP64 oracle's relaxation sweep on the host cores, on a bounded
     sample: consecutive sweeps of the same grid (the schedule's weights in
@@ -186,14 +250,19 @@ def main():
 
     ch = make_channel(wl, STP_MIXED, args.rtol)
     t_mixed, acc_mixed, st_mixed = time_steps(ch, args.steps, args.warmup, "mixed")
+    f_mixed = fields_of(ch)
     ch.close()
     del ch
     torch.cuda.empty_cache()
 
     fp64 = None
+    f_fp64 = None
+    errors = {}
     if not args.no_fp64:
         ch = make_channel(wl, STP_FP64, args.rtol)
         t64, acc64, _ = time_steps(ch, args.steps, args.warmup, "fp64")
+        f_fp64 = fields_of(ch)
+        errors["mixed"] = field_errors(f_mixed, f_fp64)
         fp64 = {"steps_per_s": round(args.steps / t64, 4), "ms_per_step": round(1e3 * t64 / args.steps, 2),
                 "sweeps_per_step": acc64["sweeps"] / args.steps,
                 "gcell_updates_per_s": round(acc64["sweeps"] * n / t64 / 1e9, 2),
@@ -218,6 +287,8 @@ def main():
                    "relres_prev_last": stl["relres_prev"], "relres_learned_last": stl["relres_learned"],
                    "corrections_per_step": accl["corrections"] / args.steps,
                    "weights": os.path.relpath(weights, ROOT)}
+            if f_fp64 is not None:
+                errors[label] = field_errors(fields_of(ch), f_fp64)
             ch.close()
             torch.cuda.empty_cache()
             return out
@@ -229,6 +300,9 @@ def main():
 
     roof = roofline_from_steps(n, acc_mixed, 4, "k_relax_fused<float,4,8>")
     roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
+    del f_mixed, f_fp64
+    torch.cuda.empty_cache()
+    table = None if args.no_table else relax_sweep_table(wl)
     cpu = None if args.no_cpu else cpu_baseline(wl)
 
     value = acc_mixed["sweeps"] * n / t_mixed / 1e9
@@ -251,6 +325,8 @@ def main():
         "learned_mixed": learned,
         "learned_mixed_trained_256x128x128": learned_256,
         "learned_mixed_correction": learned_cc,
+        "error_vs_fp64": errors or None,
+        "relax_sweeps": table,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
