@@ -32,8 +32,8 @@ FIXED_CYCLES = False  # set by --fixed-cycles: repeat the 1e-3 cycle instead of 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
-    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--workload", default="les_channel_512x256x192")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
@@ -47,13 +47,14 @@ def parse():
     return ap.parse_args()
 
 
-def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0):
+def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap_order=0):
     import torch
     from paper_1511_07800_amd import Channel, inputs
     ch = Channel(wl["nx"], wl["ny"], wl["nz"], wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"],
                  dt=wl["dt"], les=wl["les"], cs=wl.get("cs", 0.1), vd_a=wl.get("vd_a", 25.0), precision=precision,
                  poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=0 if FIXED_CYCLES else 1,
-                 srj_reduction=wl.get("srj_reduction", 1e-3), learned_correction=learned_correction)
+                 srj_reduction=wl.get("srj_reduction", 1e-3), learned_correction=learned_correction,
+                 extrap_order=extrap_order)
     u, v, w = inputs.channel_state(wl["nx"], wl["ny"], wl["nz"], wl["lz"], wl["nu"], wl["dpdx"],
                                    noise=wl.get("noise", 0.0), seed=wl.get("seed", 0))
     for k, a in enumerate((u, v, w)):
@@ -83,6 +84,7 @@ def time_steps(ch, steps, warmup, label):
               f"ms {st['ms_total']:.1f} (poisson {st['ms_poisson']:.1f}, sweeps {st['poisson']['ms_relax']:.1f}) "
               f"max_div {st['max_div']:.1e}" + (f" corrections {st['poisson']['corrections']}"
                                                  if st['poisson']['corrections'] else "") +
+              (f" extrap order {st['extrap_used']} guess {st['relres_extrap']:.2e}" if st['relres_extrap'] > 0 else "") +
               (f" net {st['ms_net']:.1f} ms relres p^n {st['relres_prev']:.2e} "
                                                  f"guess {st['relres_learned']:.2e}" if st['ms_net'] > 0 else ""),
               flush=True)
@@ -255,6 +257,16 @@ def main():
     del ch
     torch.cuda.empty_cache()
 
+    # the same with the guess extrapolated in time from the last solutions
+    ch = make_channel(wl, STP_MIXED, args.rtol, extrap_order=2)
+    t_ex, acc_ex, _ = time_steps(ch, args.steps, args.warmup, "extrap+mixed")
+    extrap = {"steps_per_s": round(args.steps / t_ex, 4), "ms_per_step": round(1e3 * t_ex / args.steps, 2),
+              "sweeps_per_step": acc_ex["sweeps"] / args.steps}
+    f_extrap = fields_of(ch)
+    ch.close()
+    del ch
+    torch.cuda.empty_cache()
+
     fp64 = None
     f_fp64 = None
     errors = {}
@@ -263,6 +275,7 @@ def main():
         t64, acc64, _ = time_steps(ch, args.steps, args.warmup, "fp64")
         f_fp64 = fields_of(ch)
         errors["mixed"] = field_errors(f_mixed, f_fp64)
+        errors["extrap+mixed"] = field_errors(f_extrap, f_fp64)
         fp64 = {"steps_per_s": round(args.steps / t64, 4), "ms_per_step": round(1e3 * t64 / args.steps, 2),
                 "sweeps_per_step": acc64["sweeps"] / args.steps,
                 "gcell_updates_per_s": round(acc64["sweeps"] * n / t64 / 1e9, 2),
@@ -274,17 +287,21 @@ def main():
     learned = None
     learned_256 = None
     learned_cc = None
+    learned_ex = None
+    learned_all = None
     if not args.no_learned:
         from paper_1511_07800_amd import STP_WS_LEARNED, warmstart
 
-        def run_learned(weights, label, correction=0):
-            ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED, learned_correction=correction)
+        def run_learned(weights, label, correction=0, extrap_order=0):
+            ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED, learned_correction=correction,
+                              extrap_order=extrap_order)
             ch.net_init(training=False)
             warmstart.load_weights(ch, weights)
             tl, accl, stl = time_steps(ch, args.steps, args.warmup, label)
             out = {"steps_per_s": round(args.steps / tl, 4), "ms_per_step": round(1e3 * tl / args.steps, 2),
                    "sweeps_per_step": accl["sweeps"] / args.steps, "ms_net_last": round(stl["ms_net"], 2),
                    "relres_prev_last": stl["relres_prev"], "relres_learned_last": stl["relres_learned"],
+                   "relres_extrap_last": stl["relres_extrap"] if extrap_order else None,
                    "corrections_per_step": accl["corrections"] / args.steps,
                    "weights": os.path.relpath(weights, ROOT)}
             if f_fp64 is not None:
@@ -297,10 +314,13 @@ def main():
         learned = run_learned(os.path.join(wdir, "warmstart_les512.npy"), "learned+mixed")
         learned_256 = run_learned(os.path.join(wdir, "warmstart_les.npy"), "learned(256-trained)+mixed")
         learned_cc = run_learned(os.path.join(wdir, "warmstart_les512.npy"), "learned+correction+mixed", correction=1)
+        learned_ex = run_learned(os.path.join(wdir, "warmstart_les512.npy"), "learned+extrap+mixed", extrap_order=2)
+        learned_all = run_learned(os.path.join(wdir, "warmstart_les512.npy"), "learned+extrap+correction+mixed",
+                                  correction=1, extrap_order=2)
 
     roof = roofline_from_steps(n, acc_mixed, 4, "k_relax_fused<float,4,8>")
     roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
-    del f_mixed, f_fp64
+    del f_mixed, f_extrap, f_fp64
     torch.cuda.empty_cache()
     table = None if args.no_table else relax_sweep_table(wl)
     cpu = None if args.no_cpu else cpu_baseline(wl)
@@ -315,16 +335,25 @@ def main():
                    "poisson_rtol": args.rtol, "dt": wl["dt"], "les": wl["les"], "init": "laminar+10% noise",
                    "srj_cycles": "fixed 1e-3" if FIXED_CYCLES else "adaptive"},
         "les_steps_per_s": {"mixed": round(args.steps / t_mixed, 4), "fp64": fp64["steps_per_s"] if fp64 else None,
+                            "extrap_mixed": extrap["steps_per_s"],
                             "learned_mixed": learned["steps_per_s"] if learned else None,
-                            "learned_mixed_correction": learned_cc["steps_per_s"] if learned_cc else None},
+                            "learned_mixed_correction": learned_cc["steps_per_s"] if learned_cc else None,
+                            "learned_extrap_mixed": learned_ex["steps_per_s"] if learned_ex else None,
+                            "learned_extrap_mixed_correction": learned_all["steps_per_s"] if learned_all else None},
         "sweeps_per_step": {"mixed": acc_mixed["sweeps"] / args.steps,
                             "fp64": fp64["sweeps_per_step"] if fp64 else None,
+                            "extrap_mixed": extrap["sweeps_per_step"],
                             "learned_mixed": learned["sweeps_per_step"] if learned else None,
-                            "learned_mixed_correction": learned_cc["sweeps_per_step"] if learned_cc else None},
+                            "learned_mixed_correction": learned_cc["sweeps_per_step"] if learned_cc else None,
+                            "learned_extrap_mixed": learned_ex["sweeps_per_step"] if learned_ex else None,
+                            "learned_extrap_mixed_correction": learned_all["sweeps_per_step"] if learned_all else None},
         "fp64": fp64,
+        "extrap_mixed": extrap,
         "learned_mixed": learned,
         "learned_mixed_trained_256x128x128": learned_256,
         "learned_mixed_correction": learned_cc,
+        "learned_extrap_mixed": learned_ex,
+        "learned_extrap_mixed_correction": learned_all,
         "error_vs_fp64": errors or None,
         "relax_sweeps": table,
         "roofline": roof,

@@ -116,6 +116,12 @@ typedef struct {
                                    not converged, try p + s_r y(r, p) from the network (a coarse
                                    correction of the residual r) and keep it when its FP64 residual is
                                    smaller; the stop test is unchanged.  0: off.  Not used in FP64 mode. */
+    int32_t extrap_order;      /* Poisson initial guess from the last solutions: 0 starts from p^n; 1 or 2
+                                  from whichever has the least FP64 residual of p^n and its extrapolations
+                                  in time of order 1 (2 p^n - p^{n-1}) and, for 2, order 2
+                                  (3 (p^n - p^{n-1}) + p^{n-2}), as far as earlier solutions exist; the
+                                  learned warm start then refines that guess.  Needs STP_WS_PREV or
+                                  STP_WS_LEARNED.  The stop test is unchanged. */
     void* stream;              /* hipStream_t for all work */
 } stp_config;
 
@@ -144,11 +150,12 @@ typedef struct {
     double nut_max;    /* max nu_T */
     double ms_total;   /* wall time of the step (stream-ordered events), ms */
     double ms_poisson; /* of which the Poisson solve, ms */
-    double relres_prev;    /* learned warm start: relative residual of p^n ... */
-    double relres_learned; /* ... and of the network's guess (0 when not used) */
+    double relres_prev;    /* learned warm start or extrapolation: relative residual of p^n ... */
+    double relres_learned; /* ... of the network's guess (0 when not used) */
     int32_t learned_used;  /* 1 if the solve started from the network's guess */
-    int32_t pad;
+    int32_t extrap_used;   /* extrapolation order of the guess kept (0: p^n) */
     double ms_net;         /* network inference time, ms */
+    double relres_extrap;  /* ... and of the extrapolated guess kept (0 when extrap_order = 0) */
 } stp_step_stats;
 
 /* Bytes of device workspace the configuration needs (0 if cfg is invalid). */

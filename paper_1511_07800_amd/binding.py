@@ -30,7 +30,8 @@ class Config(ctypes.Structure):
                 ("srj_m", ctypes.c_int32), ("srj_omega", ctypes.POINTER(ctypes.c_double)),
                 ("srj_reduction", ctypes.c_double), ("mixed_inner", ctypes.c_int32),
                 ("srj_adaptive", ctypes.c_int32), ("tblock", ctypes.c_int32),
-                ("cn_tol", ctypes.c_double), ("learned_correction", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("cn_tol", ctypes.c_double), ("learned_correction", ctypes.c_int32), ("extrap_order", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class SolveStats(ctypes.Structure):
@@ -49,7 +50,8 @@ class StepStats(ctypes.Structure):
                 ("cfl", ctypes.c_double), ("u_centre", ctypes.c_double), ("nut_max", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("ms_poisson", ctypes.c_double),
                 ("relres_prev", ctypes.c_double), ("relres_learned", ctypes.c_double),
-                ("learned_used", ctypes.c_int32), ("pad", ctypes.c_int32), ("ms_net", ctypes.c_double)]
+                ("learned_used", ctypes.c_int32), ("extrap_used", ctypes.c_int32), ("ms_net", ctypes.c_double),
+                ("relres_extrap", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("poisson", "pad")}
@@ -126,7 +128,7 @@ class Channel:
     def __init__(self, nx, ny, nz, lx, ly, lz, nu, dpdx, dt, les=0, cs=0.1, vd_a=25.0,
                  precision=STP_FP64, warm_start=STP_WS_PREV, poisson_rtol=1e-10, poisson_maxit=1000,
                  omega=None, srj_reduction=1e-3, mixed_inner=1, tblock=4, cn_tol=1e-13, srj_adaptive=0,
-                 learned_correction=0,
+                 learned_correction=0, extrap_order=0,
                  device=None):
         import torch
         self.torch = torch
@@ -150,6 +152,7 @@ class Channel:
             cfg.srj_omega = None
         cfg.srj_reduction, cfg.mixed_inner, cfg.tblock, cfg.cn_tol = srj_reduction, mixed_inner, tblock, cn_tol
         cfg.learned_correction = int(learned_correction)
+        cfg.extrap_order = int(extrap_order)
         cfg.srj_adaptive = srj_adaptive
         cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.cfg = cfg

@@ -25,6 +25,8 @@ struct stp_ctx {
     double *u = nullptr, *v = nullptr, *w = nullptr, *p = nullptr, *ptmp = nullptr, *b = nullptr, *nut = nullptr;
     double* rhs[3] = {nullptr, nullptr, nullptr};
     double* tmp = nullptr;  // Crank-Nicolson ping-pong partner (nw values)
+    double *p1 = nullptr, *p2 = nullptr;  // p^{n-1}, p^{n-2} (extrapolated warm start)
+    int nhist = 0;                        // of them, the solutions held
     double* e[3][3] = {};   // Adams-Bashforth history, [slot][component]
     // FP32 work arrays of the mixed solve
     float *e0 = nullptr, *e1 = nullptr, *r32 = nullptr;
@@ -93,12 +95,14 @@ const char* validate(const stp_config& c)
     if (c.tblock < 1 || c.tblock > kMaxFused) return "tblock must lie in 1..5";
     if (!(c.cn_tol > 0.0 && c.cn_tol < 1.0)) return "cn_tol must lie in (0, 1)";
     if (c.learned_correction != 0 && c.learned_correction != 1) return "learned_correction must be 0 or 1";
+    if (c.extrap_order < 0 || c.extrap_order > 2) return "extrap_order must be 0, 1 or 2";
+    if (c.extrap_order > 0 && c.warm_start == STP_WS_ZERO) return "extrap_order needs STP_WS_PREV or STP_WS_LEARNED";
     return nullptr;
 }
 
 // Byte offsets of every array in the workspace.
 struct Layout {
-    size_t u, v, w, p, ptmp, b, nut, rhs[3], tmp, e[3][3], e0, e1, r32, nut32, cnd, cna, cnb, part, res, total;
+    size_t u, v, w, p, ptmp, b, nut, rhs[3], tmp, p1, p2, e[3][3], e0, e1, r32, nut32, cnd, cna, cnb, part, res, total;
 };
 
 Layout layout(const stp_config& c)
@@ -120,6 +124,8 @@ Layout layout(const stp_config& c)
     L.nut = take(n * 8);
     for (int q = 0; q < 3; ++q) L.rhs[q] = take((q == 2 ? nw : n) * 8);
     L.tmp = take(nw * 8);
+    if (c.extrap_order >= 1) L.p1 = take(n * 8);
+    if (c.extrap_order >= 2) L.p2 = take(n * 8);
     for (int sl = 0; sl < 3; ++sl)
         for (int q = 0; q < 3; ++q) L.e[sl][q] = take((q == 2 ? nw : n) * 8);
     L.e0 = take(n * 4);
@@ -542,6 +548,36 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
 
     // 5. SRJ pressure solve from the warm start (Sec. 3.4)
     if (c.warm_start == STP_WS_ZERO) CHK(fill(ctx->p, 0.0, g.n, s));
+    if (c.extrap_order > 0) {
+        // candidates: p^n, 2p^n - p^{n-1} (into ptmp), 3(p^n - p^{n-1}) + p^{n-2}
+        // (into tmp), as far as the history goes; the one of least FP64
+        // residual becomes the guess, and p^n enters the history
+        CHK(residual(g, ctx->b, ctx->p, nullptr, ctx->part, ctx->res, s));
+        if ((rc = readback(ctx)) != STP_OK) return rc;
+        const double bn = std::sqrt(ctx->host[RES_B2]);
+        const double fb = bn > 1e-300 ? bn : 1e-300;
+        const double r0 = std::sqrt(ctx->host[RES_R2]);
+        double rbest = r0;
+        int best = 0;
+        double* cand[3] = {ctx->p, ctx->ptmp, ctx->tmp};
+        for (int order = 1; order <= std::min(c.extrap_order, ctx->nhist); ++order) {
+            CHK(extrapolate(ctx->p, ctx->p1, ctx->p2, order, cand[order], g.n, s));
+            CHK(residual(g, ctx->b, cand[order], nullptr, ctx->part, ctx->res, s));
+            if ((rc = readback(ctx)) != STP_OK) return rc;
+            const double r = std::sqrt(ctx->host[RES_R2]);
+            if (std::isfinite(r) && r < rbest) {
+                rbest = r;
+                best = order;
+            }
+        }
+        if (c.extrap_order >= 2 && ctx->nhist >= 1) CHK(copy(ctx->p2, ctx->p1, g.n, s));
+        CHK(copy(ctx->p1, ctx->p, g.n, s));
+        ctx->nhist = std::min(ctx->nhist + 1, c.extrap_order);
+        if (best > 0) CHK(copy(ctx->p, cand[best], g.n, s));
+        st.relres_prev = r0 / fb;
+        st.relres_extrap = rbest / fb;
+        st.extrap_used = best;
+    }
     if (c.warm_start == STP_WS_LEARNED) {
         if (!ctx->net) {
             ctx->err = "STP_WS_LEARNED needs stp_net_init";
@@ -559,7 +595,7 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
         const double r_net = std::sqrt(ctx->host[RES_R2]);
         const double bn = std::sqrt(ctx->host[RES_B2]);
         const double fb = bn > 1e-300 ? bn : 1e-300;
-        st.relres_prev = r_prev / fb;
+        if (c.extrap_order == 0) st.relres_prev = r_prev / fb;
         st.relres_learned = r_net / fb;
         if (std::isfinite(r_net) && r_net < r_prev) {
             CHK(copy(ctx->p, ctx->ptmp, g.n, s));
@@ -642,6 +678,8 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
     ctx->nut = (double*)(base + L.nut);
     for (int q = 0; q < 3; ++q) ctx->rhs[q] = (double*)(base + L.rhs[q]);
     ctx->tmp = (double*)(base + L.tmp);
+    if (c.extrap_order >= 1) ctx->p1 = (double*)(base + L.p1);
+    if (c.extrap_order >= 2) ctx->p2 = (double*)(base + L.p2);
     for (int sl = 0; sl < 3; ++sl)
         for (int q = 0; q < 3; ++q) ctx->e[sl][q] = (double*)(base + L.e[sl][q]);
     ctx->e0 = (float*)(base + L.e0);

@@ -51,6 +51,9 @@ hipError_t fill(double* a, double v, long long n, hipStream_t s);
 hipError_t fill(float* a, float v, long long n, hipStream_t s);
 hipError_t copy(double* dst, const double* src, long long n, hipStream_t s);
 hipError_t copy(float* dst, const float* src, long long n, hipStream_t s);
+// out = 2p - p1 (order 1) or 3(p - p1) + p2 (order 2)
+hipError_t extrapolate(const double* p, const double* p1, const double* p2, int order, double* out, long long n,
+                       hipStream_t s);
 hipError_t sumsq_into(const double* a, long long n, double* part, double* res, int slot, hipStream_t s);
 hipError_t zero_walls(const Geo& g, double* w, hipStream_t s);
 

@@ -107,6 +107,16 @@ __global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, lon
         d[q] = s[q];
 }
 
+// Polynomial extrapolation in time of the last solutions p = p^n, p1 = p^{n-1},
+// p2 = p^{n-2} to the next step: order 1 gives 2p - p1, order 2 gives
+// 3(p - p1) + p2.
+__global__ void k_extrapolate(const double* __restrict__ p, const double* __restrict__ p1,
+                              const double* __restrict__ p2, int order, double* __restrict__ out, long long n)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        out[q] = order == 1 ? 2.0 * p[q] - p1[q] : 3.0 * (p[q] - p1[q]) + p2[q];
+}
+
 __global__ void k_copy32(float* __restrict__ d, const float* __restrict__ s, long long n)
 {
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
@@ -662,6 +672,13 @@ hipError_t fill(float* a, float v, long long n, hipStream_t s)
 hipError_t copy(double* dst, const double* src, long long n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_copy, dim3(grid1d(n)), dim3(kBlock1d), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+hipError_t extrapolate(const double* p, const double* p1, const double* p2, int order, double* out, long long n,
+                       hipStream_t s)
+{
+    if (order != 1 && order != 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_extrapolate, dim3(grid1d(n)), dim3(kBlock1d), 0, s, p, p1, p2, order, out, n);
     return hipGetLastError();
 }
 hipError_t copy(float* dst, const float* src, long long n, hipStream_t s)

@@ -56,9 +56,13 @@ def test_workspace_bytes_valid_and_invalid():
     assert n_ok % 256 == 0 or n_ok > 0
     big = lib.stp_workspace_bytes(ctypes.byref(cfg(nx=64)))
     assert big > n_ok
+    # the extrapolated warm start keeps p^{n-1} (order 1) and p^{n-2} (order 2)
+    for order in (1, 2):
+        assert lib.stp_workspace_bytes(ctypes.byref(cfg(extrap_order=order))) == n_ok + order * 8 * n
     for bad in (dict(nz=1), dict(nx=0), dict(nu=0.0), dict(dt=-1.0), dict(lx=float("nan")),
                 dict(precision=7), dict(poisson_maxit=0), dict(poisson_rtol=-1.0), dict(srj_reduction=1.5),
-                dict(les=2), dict(tblock=-1), dict(tblock=6), dict(cn_tol=2.0), dict(srj_m=4)):
+                dict(les=2), dict(tblock=-1), dict(tblock=6), dict(cn_tol=2.0), dict(srj_m=4),
+                dict(extrap_order=3), dict(extrap_order=1, warm_start=1)):
         assert lib.stp_workspace_bytes(ctypes.byref(cfg(**bad))) == 0, bad
     assert lib.stp_workspace_bytes(None) == 0
 
