@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start run")
     ap.add_argument("--no-table", action="store_true", help="skip the sweep-rate table")
+    ap.add_argument("--weights", default="warmstart_les512_both.npy",
+                    help="network weights of the learned variants (file in paper_1511_07800_amd/weights)")
     ap.add_argument("--fixed-cycles", action="store_true", help="repeat the fixed 1e-3 SRJ cycle (no adaptive sizing)")
     ap.add_argument("--sweeps", type=int, default=200, help="sweeps in the kernel roofline timing")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -311,11 +313,11 @@ def main():
             return out
 
         wdir = os.path.join(ROOT, "paper_1511_07800_amd", "weights")
-        learned = run_learned(os.path.join(wdir, "warmstart_les512.npy"), "learned+mixed")
+        learned = run_learned(os.path.join(wdir, args.weights), "learned+mixed")
         learned_256 = run_learned(os.path.join(wdir, "warmstart_les.npy"), "learned(256-trained)+mixed")
-        learned_cc = run_learned(os.path.join(wdir, "warmstart_les512.npy"), "learned+correction+mixed", correction=1)
-        learned_ex = run_learned(os.path.join(wdir, "warmstart_les512.npy"), "learned+extrap+mixed", extrap_order=2)
-        learned_all = run_learned(os.path.join(wdir, "warmstart_les512.npy"), "learned+extrap+correction+mixed",
+        learned_cc = run_learned(os.path.join(wdir, args.weights), "learned+correction+mixed", correction=1)
+        learned_ex = run_learned(os.path.join(wdir, args.weights), "learned+extrap+mixed", extrap_order=2)
+        learned_all = run_learned(os.path.join(wdir, args.weights), "learned+extrap+correction+mixed",
                                   correction=1, extrap_order=2)
 
     roof = roofline_from_steps(n, acc_mixed, 4, "k_relax_fused<float,4,8>")

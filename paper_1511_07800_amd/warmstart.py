@@ -38,16 +38,39 @@ def make_channel(wl, precision=STP_MIXED, rtol=1e-8, warm_start=STP_WS_PREV, see
     return ch
 
 
-def generate_pairs(ch, nsteps, every, skip=0, log=print):
+def extrapolated_base(ch, b, hist):
+    """The guess the library's extrapolated warm start keeps: of p^n and its
+    extrapolations 2p^n - p^{n-1}, 3(p^n - p^{n-1}) + p^{n-2} (hist: newest
+    last), the one of least residual for b."""
+    cands = [hist[-1]]
+    if len(hist) >= 2:
+        cands.append(2.0 * hist[-1] - hist[-2])
+    if len(hist) >= 3:
+        cands.append(3.0 * (hist[-1] - hist[-2]) + hist[-3])
+    r = [ch.residual_norm(b, c) for c in cands]
+    return cands[min(range(len(r)), key=lambda i: r[i])]
+
+
+def generate_pairs(ch, nsteps, every, skip=0, log=print, base="prev"):
     """Run nsteps time steps; after the first `skip`, keep every `every`-th
-    step's (b, p^n, p^{n+1}) as device tensors."""
+    step's (b, guess, p^{n+1}) as device tensors, with guess = p^n
+    (base "prev"), the extrapolated guess ("extrap"), or one triple of each
+    ("both", the extrapolated one only where it differs from p^n)."""
     pairs = []
+    hist = [ch.field(STP_P).clone()]
     for n in range(nsteps):
         keep = n >= skip and (n - skip) % every == 0
-        p_prev = ch.field(STP_P).clone() if keep else None
         st = ch.step(1)
+        p_next = ch.field(STP_P).clone()
         if keep:
-            pairs.append((ch.field(STP_RHS).clone(), p_prev, ch.field(STP_P).clone()))
+            b = ch.field(STP_RHS).clone()
+            if base in ("prev", "both"):
+                pairs.append((b, hist[-1], p_next))
+            if base in ("extrap", "both"):
+                g = extrapolated_base(ch, b, hist)
+                if base == "extrap" or g is not hist[-1]:
+                    pairs.append((b, g, p_next))
+        hist = (hist + [p_next])[-3:]
         if (n + 1) % 50 == 0:
             log(f"  data step {n + 1}/{nsteps}: sweeps {st['poisson']['sweeps']} relres0 "
                 f"{st['poisson']['relres0']:.2e} cfl {st['cfl']:.3f}")
@@ -128,15 +151,18 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--seed", type=int, default=None, help="noise seed of the data run (default: the workload's)")
+    ap.add_argument("--base", choices=("prev", "extrap", "both"), default="prev",
+                    help="guess the triples start from: p^n, the extrapolated guess, or both")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     wl = workloads.params(args.workload)
     log = lambda s: print(s, flush=True)
     t0 = time.perf_counter()
-    ch = make_channel(wl, STP_MIXED, args.rtol)
+    ch = make_channel(wl, STP_MIXED, args.rtol, seed=args.seed, srj_adaptive=1)
     ch.net_init(training=True, seed=1)
-    pairs = generate_pairs(ch, args.steps, args.every, args.skip, log)
+    pairs = generate_pairs(ch, args.steps, args.every, args.skip, log, base=args.base)
     ntrain = int(0.8 * len(pairs))
     train_set, held = pairs[:ntrain], pairs[ntrain:]
     log(f"{len(pairs)} triples ({ntrain} train, {len(held)} held out), data {time.perf_counter() - t0:.1f} s")
@@ -146,7 +172,8 @@ def main():
     s_prev = sweeps_to_tolerance(ch, held, args.rtol, False)
     s_net = sweeps_to_tolerance(ch, held, args.rtol, True)
     summary = {
-        "workload": args.workload, "steps": args.steps, "every": args.every, "skip": args.skip,
+        "workload": args.workload, "seed": args.seed if args.seed is not None else wl.get("seed"),
+        "base": args.base, "steps": args.steps, "every": args.every, "skip": args.skip,
         "train_triples": ntrain, "held_out": len(held), "epochs": args.epochs, "lr": args.lr,
         "loss_by_epoch": hist,
         "held_relres_prev_mean": float(np.mean([q["relres_prev"] for q in q1])),
