@@ -548,6 +548,7 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
 
     // 5. SRJ pressure solve from the warm start (Sec. 3.4)
     if (c.warm_start == STP_WS_ZERO) CHK(fill(ctx->p, 0.0, g.n, s));
+    double guess_res = -1.0;  // residual norm of ctx->p when already known
     if (c.extrap_order > 0) {
         // candidates: p^n, 2p^n - p^{n-1} (into ptmp), 3(p^n - p^{n-1}) + p^{n-2}
         // (into tmp), as far as the history goes; the one of least FP64
@@ -577,6 +578,7 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
         st.relres_prev = r0 / fb;
         st.relres_extrap = rbest / fb;
         st.extrap_used = best;
+        guess_res = rbest;
     }
     if (c.warm_start == STP_WS_LEARNED) {
         if (!ctx->net) {
@@ -587,9 +589,12 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
         CHK(hipEventRecord(ctx->ev[4], s));
         CHK(ctx->net->predict(ctx->b, ctx->p, ctx->ptmp));
         CHK(hipEventRecord(ctx->ev[5], s));
-        CHK(residual(g, ctx->b, ctx->p, nullptr, ctx->part, ctx->res, s));
-        if ((rc = readback(ctx)) != STP_OK) return rc;
-        const double r_prev = std::sqrt(ctx->host[RES_R2]);
+        if (guess_res < 0.0) {
+            CHK(residual(g, ctx->b, ctx->p, nullptr, ctx->part, ctx->res, s));
+            if ((rc = readback(ctx)) != STP_OK) return rc;
+            guess_res = std::sqrt(ctx->host[RES_R2]);
+        }
+        const double r_prev = guess_res;
         CHK(residual(g, ctx->b, ctx->ptmp, nullptr, ctx->part, ctx->res, s));
         if ((rc = readback(ctx)) != STP_OK) return rc;
         const double r_net = std::sqrt(ctx->host[RES_R2]);

@@ -154,6 +154,7 @@ def main():
     ap.add_argument("--seed", type=int, default=None, help="noise seed of the data run (default: the workload's)")
     ap.add_argument("--base", choices=("prev", "extrap", "both"), default="prev",
                     help="guess the triples start from: p^n, the extrapolated guess, or both")
+    ap.add_argument("--init", default=None, help="weights to start from (default: random initialisation)")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -162,6 +163,8 @@ def main():
     t0 = time.perf_counter()
     ch = make_channel(wl, STP_MIXED, args.rtol, seed=args.seed, srj_adaptive=1)
     ch.net_init(training=True, seed=1)
+    if args.init:
+        load_weights(ch, args.init)
     pairs = generate_pairs(ch, args.steps, args.every, args.skip, log, base=args.base)
     ntrain = int(0.8 * len(pairs))
     train_set, held = pairs[:ntrain], pairs[ntrain:]
@@ -173,7 +176,8 @@ def main():
     s_net = sweeps_to_tolerance(ch, held, args.rtol, True)
     summary = {
         "workload": args.workload, "seed": args.seed if args.seed is not None else wl.get("seed"),
-        "base": args.base, "steps": args.steps, "every": args.every, "skip": args.skip,
+        "base": args.base, "init": os.path.basename(args.init) if args.init else None,
+        "steps": args.steps, "every": args.every, "skip": args.skip,
         "train_triples": ntrain, "held_out": len(held), "epochs": args.epochs, "lr": args.lr,
         "loss_by_epoch": hist,
         "held_relres_prev_mean": float(np.mean([q["relres_prev"] for q in q1])),
