@@ -9,6 +9,7 @@
 #include "stp_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace stp {
 
@@ -195,39 +196,57 @@ __global__ __launch_bounds__(256) void k_nut(Geo g, int kchunk, const double* __
         const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
         const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
         const double dz = 1.0 / g.idz;
+        // u and v with the odd wall ghosts; w's wall planes hold 0
+        auto U = [&](int ii, int jj, int kk) -> double {
+            if (kk < 0) return -u[at(g, ii, jj, 0)];
+            if (kk >= g.nz) return -u[at(g, ii, jj, g.nz - 1)];
+            return u[at(g, ii, jj, kk)];
+        };
+        auto V = [&](int ii, int jj, int kk) -> double {
+            if (kk < 0) return -v[at(g, ii, jj, 0)];
+            if (kk >= g.nz) return -v[at(g, ii, jj, g.nz - 1)];
+            return v[at(g, ii, jj, kk)];
+        };
+        auto Wf = [&](int ii, int jj, int kk) -> double { return w[at(g, ii, jj, kk)]; };
+        const int is[2] = {i, ip}, ism[2] = {im, i};
+        const int js[2] = {j, jp}, jsm[2] = {jm, j};
+        // x-z edge (i + di, kk) on row j and y-z edge (j + di, kk) on column i
+        auto s13at = [&](int di, int kk) {
+            return 0.5 * ((U(is[di], j, kk) - U(is[di], j, kk - 1)) * g.idz + (Wf(is[di], j, kk) - Wf(ism[di], j, kk)) * g.idx);
+        };
+        auto s23at = [&](int di, int kk) {
+            return 0.5 * ((V(i, js[di], kk) - V(i, js[di], kk - 1)) * g.idz + (Wf(i, js[di], kk) - Wf(i, jsm[di], kk)) * g.idy);
+        };
+        // Along the march the edges above plane k become the edges below
+        // plane k + 1, and the column's values on plane k + 1 are those of the
+        // next step: both stay in registers.
+        double s13lo[2] = {s13at(0, k0), s13at(1, k0)}, s23lo[2] = {s23at(0, k0), s23at(1, k0)};
+        double uc = U(i, j, k0), ue = U(ip, j, k0), vc = V(i, j, k0), vn = V(i, jp, k0), wc = Wf(i, j, k0);
         for (int k = k0; k < k1; ++k) {
-            // u and v on planes k-1, k, k+1 with the odd wall ghosts
-            auto U = [&](int ii, int jj, int kk) -> double {
-                if (kk < 0) return -u[at(g, ii, jj, 0)];
-                if (kk >= g.nz) return -u[at(g, ii, jj, g.nz - 1)];
-                return u[at(g, ii, jj, kk)];
-            };
-            auto V = [&](int ii, int jj, int kk) -> double {
-                if (kk < 0) return -v[at(g, ii, jj, 0)];
-                if (kk >= g.nz) return -v[at(g, ii, jj, g.nz - 1)];
-                return v[at(g, ii, jj, kk)];
-            };
-            auto Wf = [&](int ii, int jj, int kk) -> double { return w[at(g, ii, jj, kk)]; };  // walls hold 0
-            const double s11 = (U(ip, j, k) - U(i, j, k)) * g.idx;
-            const double s22 = (V(i, jp, k) - V(i, j, k)) * g.idy;
-            const double s33 = (Wf(i, j, k + 1) - Wf(i, j, k)) * g.idz;
+            const double uS = U(i, jm, k), uSE = U(ip, jm, k), uN = U(i, jp, k), uNE = U(ip, jp, k);
+            const double vW = V(im, j, k), vE = V(ip, j, k), vNW = V(im, jp, k), vNE = V(ip, jp, k);
+            const double uc1 = U(i, j, k + 1), ue1 = U(ip, j, k + 1), vc1 = V(i, j, k + 1), vn1 = V(i, jp, k + 1);
+            const double wc1 = Wf(i, j, k + 1), we1 = Wf(ip, j, k + 1), ww1 = Wf(im, j, k + 1);
+            const double wn1 = Wf(i, jp, k + 1), ws1 = Wf(i, jm, k + 1);
+            const double s11 = (ue - uc) * g.idx;
+            const double s22 = (vn - vc) * g.idy;
+            const double s33 = (wc1 - wc) * g.idz;
+            const double s13hi[2] = {0.5 * ((uc1 - uc) * g.idz + (wc1 - ww1) * g.idx),
+                                     0.5 * ((ue1 - ue) * g.idz + (we1 - wc1) * g.idx)};
+            const double s23hi[2] = {0.5 * ((vc1 - vc) * g.idz + (wc1 - ws1) * g.idy),
+                                     0.5 * ((vn1 - vn) * g.idz + (wn1 - wc1) * g.idy)};
+            // x-y edges (i + di, j + dj) on plane k
+            const double s12[4] = {0.5 * ((uc - uS) * g.idy + (vc - vW) * g.idx),
+                                   0.5 * ((ue - uSE) * g.idy + (vE - vc) * g.idx),
+                                   0.5 * ((uN - uc) * g.idy + (vn - vNW) * g.idx),
+                                   0.5 * ((uNE - ue) * g.idy + (vNE - vn) * g.idx)};
             double a12 = 0.0, a13 = 0.0, a23 = 0.0;
-            const int is[2] = {i, ip}, ism[2] = {im, i};
-            const int js[2] = {j, jp}, jsm[2] = {jm, j};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int di = e & 1, dj = e >> 1;
-                // x-y edge (i+di, j+dj) on plane k
-                const double s12 = 0.5 * ((U(is[di], js[dj], k) - U(is[di], jsm[dj], k)) * g.idy +
-                                          (V(is[di], js[dj], k) - V(ism[di], js[dj], k)) * g.idx);
-                // x-z edge (i+di, k+dj) on row j
-                const int kk = k + dj;
-                const double s13 = 0.5 * ((U(is[di], j, kk) - U(is[di], j, kk - 1)) * g.idz +
-                                          (Wf(is[di], j, kk) - Wf(ism[di], j, kk)) * g.idx);
-                // y-z edge (j+di, k+dj) on column i
-                const double s23 = 0.5 * ((V(i, js[di], kk) - V(i, js[di], kk - 1)) * g.idz +
-                                          (Wf(i, js[di], kk) - Wf(i, jsm[di], kk)) * g.idy);
-                a12 += 0.25 * s12 * s12;
+                const double s13 = dj ? s13hi[di] : s13lo[di];
+                const double s23 = dj ? s23hi[di] : s23lo[di];
+                a12 += 0.25 * s12[e] * s12[e];
                 a13 += 0.25 * s13 * s13;
                 a23 += 0.25 * s23 * s23;
             }
@@ -238,6 +257,15 @@ __global__ __launch_bounds__(256) void k_nut(Geo g, int kchunk, const double* __
             const double val = nu + l * l * sqrt(s2);
             nut[at(g, i, j, k)] = val;
             vmax = fmax(vmax, val);
+            s13lo[0] = s13hi[0];
+            s13lo[1] = s13hi[1];
+            s23lo[0] = s23hi[0];
+            s23lo[1] = s23hi[1];
+            uc = uc1;
+            ue = ue1;
+            vc = vc1;
+            vn = vn1;
+            wc = wc1;
         }
     }
     const double r = block_reduce<true>(vmax, lds);
@@ -312,40 +340,59 @@ __global__ __launch_bounds__(256) void k_mom_u(Geo g, int kchunk, MomArgs a)
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
-    const Nu N{a.nut, g, a.nu};
     const double* __restrict__ u = a.u;
     const double* __restrict__ v = a.v;
     const double* __restrict__ w = a.w;
+    auto C = [&](int ii, int jj, int kk) { return a.nut[at(g, ii, jj, kk)]; };
     const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+    // Carried along the march (the values of plane k + 1 become those of
+    // plane k): u at the face's column on k - 1 and k, w under the face's
+    // x-z edge, nu_T at the two centres of the face, and the x-z edge
+    // viscosity below the face.
+    double uc = u[at(g, i, j, k0)], uBraw = k0 > 0 ? u[at(g, i, j, k0 - 1)] : 0.0;
+    double wI = w[at(g, i, j, k0)], wIm = w[at(g, im, j, k0)];
+    double nC = C(i, j, k0), nWc = C(im, j, k0);
+    double nB = k0 > 0 ? 0.25 * (C(im, j, k0 - 1) + C(i, j, k0 - 1) + nWc + nC) : a.nu;
     for (int k = k0; k < k1; ++k) {
         const long long c = at(g, i, j, k);
-        const double uc = u[c];
+        const bool up = k + 1 < g.nz;
+        const double uTraw = up ? u[c + g.plane] : 0.0;
         const double uE = u[at(g, ip, j, k)], uW = u[at(g, im, j, k)];
         const double uN = u[at(g, i, jp, k)], uS = u[at(g, i, jm, k)];
-        const double uT = k + 1 < g.nz ? u[c + g.plane] : -uc;
-        const double uB = k > 0 ? u[c - g.plane] : -uc;
+        const double uT = up ? uTraw : -uc;
+        const double uB = k > 0 ? uBraw : -uc;
         // convection, divergence form
         const double ue = 0.5 * (uc + uE), uw = 0.5 * (uW + uc);
         const double cx = (ue * ue - uw * uw) * g.idx;
-        const double vn = 0.5 * (v[at(g, im, jp, k)] + v[at(g, i, jp, k)]);
-        const double vs = 0.5 * (v[at(g, im, j, k)] + v[at(g, i, j, k)]);
+        const double vImjp = v[at(g, im, jp, k)], vIjp = v[at(g, i, jp, k)];
+        const double vImj = v[at(g, im, j, k)], vIj = v[at(g, i, j, k)];
+        const double vn = 0.5 * (vImjp + vIjp);
+        const double vs = 0.5 * (vImj + vIj);
         const double cy = (vn * 0.5 * (uc + uN) - vs * 0.5 * (uS + uc)) * g.idy;
-        const double wt = 0.5 * (w[at(g, im, j, k + 1)] + w[at(g, i, j, k + 1)]);
-        const double wb = 0.5 * (w[at(g, im, j, k)] + w[at(g, i, j, k)]);
+        const double wIm1 = w[at(g, im, j, k + 1)], wI1 = w[at(g, i, j, k + 1)];
+        const double wt = 0.5 * (wIm1 + wI1);
+        const double wb = 0.5 * (wIm + wI);
         const double cz = (wt * 0.5 * (uc + uT) - wb * 0.5 * (uB + uc)) * g.idz;
         // viscous terms
-        const double nE = N.c(i, j, k), nW = N.c(im, j, k);
-        const double nN = N.xy(im, i, j, jp, k), nS = N.xy(im, i, jm, j, k);
-        const double nT = N.xz(im, i, j, k + 1), nB = N.xz(im, i, j, k);
+        const double nE = nC, nW = nWc;
+        const double nN = 0.25 * (nWc + nC + C(im, jp, k) + C(i, jp, k));
+        const double nS = 0.25 * (C(im, jm, k) + C(i, jm, k) + nWc + nC);
+        const double nCn = up ? C(i, j, k + 1) : 0.0, nWn = up ? C(im, j, k + 1) : 0.0;
+        const double nT = up ? 0.25 * (nWc + nC + nWn + nCn) : a.nu;
         const double dxx = (nE * (uE - uc) - nW * (uc - uW)) * g.idx2;
-        const double vy = (nN * (v[at(g, i, jp, k)] - v[at(g, im, jp, k)]) - nS * (v[at(g, i, j, k)] - v[at(g, im, j, k)])) *
-                          (g.idx * g.idy);
-        const double vz = (nT * (w[at(g, i, j, k + 1)] - w[at(g, im, j, k + 1)]) - nB * (w[at(g, i, j, k)] - w[at(g, im, j, k)])) *
-                          (g.idx * g.idz);
+        const double vy = (nN * (vIjp - vImjp) - nS * (vIj - vImj)) * (g.idx * g.idy);
+        const double vz = (nT * (wI1 - wIm1) - nB * (wI - wIm)) * (g.idx * g.idz);
         const double E = -(cx + cy + cz) + (dxx + vy + vz) - a.dpdx;
         const double Ldiff = dxx + (nN * (uN - uc) - nS * (uc - uS)) * g.idy2 + (nT * (uT - uc) - nB * (uc - uB)) * g.idz2;
         a.en[c] = E;
         a.rhs[c] = uc + a.dt * (a.beta0 * E + a.beta1 * a.e1[c] + a.beta2 * a.e2[c]) + a.half_dt * Ldiff;
+        uBraw = uc;
+        uc = uTraw;
+        wI = wI1;
+        wIm = wIm1;
+        nC = nCn;
+        nWc = nWn;
+        nB = nT;
     }
 }
 
@@ -356,38 +403,54 @@ __global__ __launch_bounds__(256) void k_mom_v(Geo g, int kchunk, MomArgs a)
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
-    const Nu N{a.nut, g, a.nu};
     const double* __restrict__ u = a.u;
     const double* __restrict__ v = a.v;
     const double* __restrict__ w = a.w;
+    auto C = [&](int ii, int jj, int kk) { return a.nut[at(g, ii, jj, kk)]; };
     const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+    // carried as in k_mom_u, with x and y exchanged
+    double vc = v[at(g, i, j, k0)], vBraw = k0 > 0 ? v[at(g, i, j, k0 - 1)] : 0.0;
+    double wJ = w[at(g, i, j, k0)], wJm = w[at(g, i, jm, k0)];
+    double nC = C(i, j, k0), nSc = C(i, jm, k0);
+    double nB = k0 > 0 ? 0.25 * (C(i, jm, k0 - 1) + C(i, j, k0 - 1) + nSc + nC) : a.nu;
     for (int k = k0; k < k1; ++k) {
         const long long c = at(g, i, j, k);
-        const double vc = v[c];
+        const bool up = k + 1 < g.nz;
+        const double vTraw = up ? v[c + g.plane] : 0.0;
         const double vE = v[at(g, ip, j, k)], vW = v[at(g, im, j, k)];
         const double vN = v[at(g, i, jp, k)], vS = v[at(g, i, jm, k)];
-        const double vT = k + 1 < g.nz ? v[c + g.plane] : -vc;
-        const double vB = k > 0 ? v[c - g.plane] : -vc;
-        const double ue = 0.5 * (u[at(g, ip, jm, k)] + u[at(g, ip, j, k)]);
-        const double uw = 0.5 * (u[at(g, i, jm, k)] + u[at(g, i, j, k)]);
+        const double vT = up ? vTraw : -vc;
+        const double vB = k > 0 ? vBraw : -vc;
+        const double uIpjm = u[at(g, ip, jm, k)], uIpj = u[at(g, ip, j, k)];
+        const double uIjm = u[at(g, i, jm, k)], uIj = u[at(g, i, j, k)];
+        const double ue = 0.5 * (uIpjm + uIpj);
+        const double uw = 0.5 * (uIjm + uIj);
         const double cx = (ue * 0.5 * (vc + vE) - uw * 0.5 * (vW + vc)) * g.idx;
         const double vn = 0.5 * (vc + vN), vs = 0.5 * (vS + vc);
         const double cy = (vn * vn - vs * vs) * g.idy;
-        const double wt = 0.5 * (w[at(g, i, jm, k + 1)] + w[at(g, i, j, k + 1)]);
-        const double wb = 0.5 * (w[at(g, i, jm, k)] + w[at(g, i, j, k)]);
+        const double wJm1 = w[at(g, i, jm, k + 1)], wJ1 = w[at(g, i, j, k + 1)];
+        const double wt = 0.5 * (wJm1 + wJ1);
+        const double wb = 0.5 * (wJm + wJ);
         const double cz = (wt * 0.5 * (vc + vT) - wb * 0.5 * (vB + vc)) * g.idz;
-        const double nE = N.xy(i, ip, jm, j, k), nW = N.xy(im, i, jm, j, k);
-        const double nN = N.c(i, j, k), nS = N.c(i, jm, k);
-        const double nT = N.yz(i, jm, j, k + 1), nB = N.yz(i, jm, j, k);
-        const double vx = (nE * (u[at(g, ip, j, k)] - u[at(g, ip, jm, k)]) - nW * (u[at(g, i, j, k)] - u[at(g, i, jm, k)])) *
-                          (g.idx * g.idy);
+        const double nE = 0.25 * (nSc + C(ip, jm, k) + nC + C(ip, j, k));
+        const double nW = 0.25 * (C(im, jm, k) + nSc + C(im, j, k) + nC);
+        const double nN = nC, nS = nSc;
+        const double nCn = up ? C(i, j, k + 1) : 0.0, nSn = up ? C(i, jm, k + 1) : 0.0;
+        const double nT = up ? 0.25 * (nSc + nC + nSn + nCn) : a.nu;
+        const double vx = (nE * (uIpj - uIpjm) - nW * (uIj - uIjm)) * (g.idx * g.idy);
         const double dyy = (nN * (vN - vc) - nS * (vc - vS)) * g.idy2;
-        const double vz = (nT * (w[at(g, i, j, k + 1)] - w[at(g, i, jm, k + 1)]) - nB * (w[at(g, i, j, k)] - w[at(g, i, jm, k)])) *
-                          (g.idy * g.idz);
+        const double vz = (nT * (wJ1 - wJm1) - nB * (wJ - wJm)) * (g.idy * g.idz);
         const double E = -(cx + cy + cz) + (vx + dyy + vz);
         const double Ldiff = (nE * (vE - vc) - nW * (vc - vW)) * g.idx2 + dyy + (nT * (vT - vc) - nB * (vc - vB)) * g.idz2;
         a.en[c] = E;
         a.rhs[c] = vc + a.dt * (a.beta0 * E + a.beta1 * a.e1[c] + a.beta2 * a.e2[c]) + a.half_dt * Ldiff;
+        vBraw = vc;
+        vc = vTraw;
+        wJ = wJ1;
+        wJm = wJm1;
+        nC = nCn;
+        nSc = nSn;
+        nB = nT;
     }
 }
 
@@ -399,68 +462,157 @@ __global__ __launch_bounds__(256) void k_mom_w(Geo g, int kchunk, MomArgs a)
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
-    const Nu N{a.nut, g, a.nu};
     const double* __restrict__ u = a.u;
     const double* __restrict__ v = a.v;
     const double* __restrict__ w = a.w;
+    auto C = [&](int ii, int jj, int kk) { return a.nut[at(g, ii, jj, kk)]; };
     const int k0 = blockIdx.z * kchunk, k1 = min(g.nz + 1, k0 + kchunk);
-    for (int k = k0; k < k1; ++k) {
+    auto wall = [&](int k) {
         const long long c = at(g, i, j, k);
-        if (k == 0 || k == g.nz) {
-            a.en[c] = 0.0;
-            a.rhs[c] = 0.0;
-            continue;
-        }
-        const double wc = w[c];
-        const double wE = w[at(g, ip, j, k)], wW = w[at(g, im, j, k)];
-        const double wN = w[at(g, i, jp, k)], wS = w[at(g, i, jm, k)];
-        const double wT = w[c + g.plane], wB = w[c - g.plane];
-        const double ue = 0.5 * (u[at(g, ip, j, k - 1)] + u[at(g, ip, j, k)]);
-        const double uw = 0.5 * (u[at(g, i, j, k - 1)] + u[at(g, i, j, k)]);
-        const double cx = (ue * 0.5 * (wc + wE) - uw * 0.5 * (wW + wc)) * g.idx;
-        const double vn = 0.5 * (v[at(g, i, jp, k - 1)] + v[at(g, i, jp, k)]);
-        const double vs = 0.5 * (v[at(g, i, j, k - 1)] + v[at(g, i, j, k)]);
-        const double cy = (vn * 0.5 * (wc + wN) - vs * 0.5 * (wS + wc)) * g.idy;
-        const double wt = 0.5 * (wc + wT), wb = 0.5 * (wB + wc);
-        const double cz = (wt * wt - wb * wb) * g.idz;
-        const double nE = N.xz(i, ip, j, k), nW = N.xz(im, i, j, k);
-        const double nN = N.yz(i, j, jp, k), nS = N.yz(i, jm, j, k);
-        const double nT = N.c(i, j, k), nB = N.c(i, j, k - 1);
-        const double vx = (nE * (u[at(g, ip, j, k)] - u[at(g, ip, j, k - 1)]) - nW * (u[at(g, i, j, k)] - u[at(g, i, j, k - 1)])) *
-                          (g.idx * g.idz);
-        const double vy = (nN * (v[at(g, i, jp, k)] - v[at(g, i, jp, k - 1)]) - nS * (v[at(g, i, j, k)] - v[at(g, i, j, k - 1)])) *
-                          (g.idy * g.idz);
-        const double dzz = (nT * (wT - wc) - nB * (wc - wB)) * g.idz2;
-        const double E = -(cx + cy + cz) + (vx + vy + dzz);
-        const double Ldiff = (nE * (wE - wc) - nW * (wc - wW)) * g.idx2 + (nN * (wN - wc) - nS * (wc - wS)) * g.idy2 + dzz;
-        a.en[c] = E;
-        a.rhs[c] = wc + a.dt * (a.beta0 * E + a.beta1 * a.e1[c] + a.beta2 * a.e2[c]) + a.half_dt * Ldiff;
+        a.en[c] = 0.0;
+        a.rhs[c] = 0.0;
+    };
+    int kb = k0;
+    if (kb == 0) {
+        wall(0);
+        kb = 1;
     }
+    const int ke = min(k1, g.nz);  // interior faces [kb, ke)
+    if (kb < ke) {
+        // Carried along the march: w at the column on k - 1 and k; u, v and
+        // nu_T on the plane of centres below the face (k - 1).
+        double wB = w[at(g, i, j, kb - 1)], wc = w[at(g, i, j, kb)];
+        double uIp0 = u[at(g, ip, j, kb - 1)], uI0 = u[at(g, i, j, kb - 1)];
+        double vJp0 = v[at(g, i, jp, kb - 1)], vJ0 = v[at(g, i, j, kb - 1)];
+        double pC = C(i, j, kb - 1), pE = C(ip, j, kb - 1), pW = C(im, j, kb - 1), pN = C(i, jp, kb - 1),
+               pS = C(i, jm, kb - 1);
+        for (int k = kb; k < ke; ++k) {
+            const long long c = at(g, i, j, k);
+            const double wE = w[at(g, ip, j, k)], wW = w[at(g, im, j, k)];
+            const double wN = w[at(g, i, jp, k)], wS = w[at(g, i, jm, k)];
+            const double wT = w[c + g.plane];
+            const double uIp1 = u[at(g, ip, j, k)], uI1 = u[at(g, i, j, k)];
+            const double vJp1 = v[at(g, i, jp, k)], vJ1 = v[at(g, i, j, k)];
+            const double ue = 0.5 * (uIp0 + uIp1);
+            const double uw = 0.5 * (uI0 + uI1);
+            const double cx = (ue * 0.5 * (wc + wE) - uw * 0.5 * (wW + wc)) * g.idx;
+            const double vn = 0.5 * (vJp0 + vJp1);
+            const double vs = 0.5 * (vJ0 + vJ1);
+            const double cy = (vn * 0.5 * (wc + wN) - vs * 0.5 * (wS + wc)) * g.idy;
+            const double wt = 0.5 * (wc + wT), wb = 0.5 * (wB + wc);
+            const double cz = (wt * wt - wb * wb) * g.idz;
+            const double cC = C(i, j, k), cE = C(ip, j, k), cW = C(im, j, k), cN = C(i, jp, k), cS = C(i, jm, k);
+            const double nE = 0.25 * (pC + pE + cC + cE), nW = 0.25 * (pW + pC + cW + cC);
+            const double nN = 0.25 * (pC + pN + cC + cN), nS = 0.25 * (pS + pC + cS + cC);
+            const double nT = cC, nB = pC;
+            const double vx = (nE * (uIp1 - uIp0) - nW * (uI1 - uI0)) * (g.idx * g.idz);
+            const double vy = (nN * (vJp1 - vJp0) - nS * (vJ1 - vJ0)) * (g.idy * g.idz);
+            const double dzz = (nT * (wT - wc) - nB * (wc - wB)) * g.idz2;
+            const double E = -(cx + cy + cz) + (vx + vy + dzz);
+            const double Ldiff = (nE * (wE - wc) - nW * (wc - wW)) * g.idx2 + (nN * (wN - wc) - nS * (wc - wS)) * g.idy2 + dzz;
+            a.en[c] = E;
+            a.rhs[c] = wc + a.dt * (a.beta0 * E + a.beta1 * a.e1[c] + a.beta2 * a.e2[c]) + a.half_dt * Ldiff;
+            wB = wc;
+            wc = wT;
+            uIp0 = uIp1;
+            uI0 = uI1;
+            vJp0 = vJp1;
+            vJ0 = vJ1;
+            pC = cC;
+            pE = cE;
+            pW = cW;
+            pN = cN;
+            pS = cS;
+        }
+    }
+    if (k1 == g.nz + 1) wall(g.nz);
 }
 
-// One Crank-Nicolson iteration for component COMP:
-// x_out = x + (R - x + h L_nu x) * inv_shift, L_nu = d_j(nu_T d_j .).
-template <int COMP>
-__global__ __launch_bounds__(256) void k_cn(Geo g, int kchunk, const double* __restrict__ nut, double nu,
-                                            const double* __restrict__ R, const double* __restrict__ x,
-                                            double* __restrict__ xo, double h, double inv_shift)
+// L_nu x = d_j(nu_T d_j x) for component COMP along the z march of the column
+// (i, j) over planes [k0, k1), with visc_apply's expression and order of
+// evaluation (so the results are identical) but the column's vertical
+// neighbours and the nu_T values and edge averages shared with the next
+// plane kept in registers: each plane loads x at k + 1 and its four lateral
+// neighbours and the nu_T values of the new plane, not the whole stencil.
+// Calls upd(k, c, L, x_c) for every face the column owns, wall(k) for w's
+// wall planes.  TC: arithmetic, TN: nu_T storage, TX: x storage.
+template <int COMP, typename TC, typename TN, typename TX, typename Upd, typename Wall>
+__device__ __forceinline__ void visc_march(const Geo& g, int i, int j, int k0, int k1, const TN* __restrict__ nut,
+                                           double nu, const TX* __restrict__ X, Upd&& upd, Wall&& wall)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= g.nx || j >= g.ny) return;
     const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
-    const Nu N{nut, g, nu};
-    const int nplanes = COMP == 2 ? g.nz + 1 : g.nz;
-    const int k0 = blockIdx.z * kchunk, k1 = min(nplanes, k0 + kchunk);
-    for (int k = k0; k < k1; ++k) {
-        const long long c = at(g, i, j, k);
-        if (COMP == 2 && (k == 0 || k == g.nz)) {
-            xo[c] = 0.0;
-            continue;
+    const long long P = g.plane;
+    const long long oc = at(g, i, j, 0), oE = at(g, ip, j, 0), oW = at(g, im, j, 0), oN = at(g, i, jp, 0),
+                    oS = at(g, i, jm, 0);
+    auto C = [&](long long o, int k) -> TC { return (TC)nut[o + P * k]; };
+    auto V = [&](long long o, int k) -> TC { return (TC)X[o + P * k]; };
+    const TC idx2 = (TC)g.idx2, idy2 = (TC)g.idy2, idz2 = (TC)g.idz2, nuT = (TC)nu, q = TC(0.25);
+
+    if constexpr (COMP == 0 || COMP == 1) {
+        // u: centre nu_T at (i, j) and (im, j), x-y edges to the north and
+        // south, x-z edges above and below.  v: the same with x and y swapped.
+        const long long oA = COMP == 0 ? oW : oS;  // the other centre of the face
+        TC xc = V(oc, k0), xBraw = k0 > 0 ? V(oc, k0 - 1) : TC(0);
+        TC cC = C(oc, k0), cA = C(oA, k0);
+        TC elo = nuT;  // vertical edge below plane k0
+        if (k0 > 0) elo = q * (C(oA, k0 - 1) + C(oc, k0 - 1) + cA + cC);
+        for (int k = k0; k < k1; ++k) {
+            const bool up = k + 1 < g.nz;
+            const TC xTraw = up ? V(oc, k + 1) : TC(0);
+            const TC cCn = up ? C(oc, k + 1) : TC(0), cAn = up ? C(oA, k + 1) : TC(0);
+            const TC xT = up ? xTraw : -xc, xB = k > 0 ? xBraw : -xc;
+            const TC xE = V(oE, k), xW = V(oW, k), xN = V(oN, k), xS = V(oS, k);
+            const TC eup = up ? q * (cA + cC + cAn + cCn) : nuT;
+            TC L;
+            if constexpr (COMP == 0) {
+                const TC en = q * (cA + cC + C(oW + (oN - oc), k) + C(oN, k));  // edge (im|i) x (j|jp)
+                const TC es = q * (C(oW + (oS - oc), k) + C(oS, k) + cA + cC);  // edge (im|i) x (jm|j)
+                L = (cC * (xE - xc) - cA * (xc - xW)) * idx2 + (en * (xN - xc) - es * (xc - xS)) * idy2 +
+                    (eup * (xT - xc) - elo * (xc - xB)) * idz2;
+            } else {
+                const TC ee = q * (cA + C(oS + (oE - oc), k) + cC + C(oE, k));  // edge (i|ip) x (jm|j)
+                const TC ew = q * (C(oS + (oW - oc), k) + cA + C(oW, k) + cC);  // edge (im|i) x (jm|j)
+                L = (ee * (xE - xc) - ew * (xc - xW)) * idx2 + (cC * (xN - xc) - cA * (xc - xS)) * idy2 +
+                    (eup * (xT - xc) - elo * (xc - xB)) * idz2;
+            }
+            upd(k, oc + P * k, L, xc);
+            xBraw = xc;
+            xc = xTraw;
+            cC = cCn;
+            cA = cAn;
+            elo = eup;
         }
-        const double xc = x[c];
-        const double L = visc_apply<COMP, double>(g, N, x, c, i, j, k, im, ip, jm, jp);
-        xo[c] = xc + (R[c] - xc + h * L) * inv_shift;
+    } else {
+        // w on z-faces: nu_T at the centres below (k - 1) and above (k), x-z
+        // edges east and west, y-z edges north and south
+        int kb = k0;
+        if (kb == 0) {
+            wall(oc);
+            kb = 1;
+        }
+        const int ke = min(k1, g.nz);  // interior planes [kb, ke)
+        if (kb < ke) {
+            TC xB = V(oc, kb - 1), xc = V(oc, kb);
+            TC pC = C(oc, kb - 1), pE = C(oE, kb - 1), pW = C(oW, kb - 1), pN = C(oN, kb - 1), pS = C(oS, kb - 1);
+            for (int k = kb; k < ke; ++k) {
+                const TC xT = V(oc, k + 1);
+                const TC xE = V(oE, k), xW = V(oW, k), xN = V(oN, k), xS = V(oS, k);
+                const TC cC = C(oc, k), cE = C(oE, k), cW = C(oW, k), cN = C(oN, k), cS = C(oS, k);
+                const TC ee = q * (pC + pE + cC + cE), ew = q * (pW + pC + cW + cC);
+                const TC en = q * (pC + pN + cC + cN), es = q * (pS + pC + cS + cC);
+                const TC L = (ee * (xE - xc) - ew * (xc - xW)) * idx2 + (en * (xN - xc) - es * (xc - xS)) * idy2 +
+                             (cC * (xT - xc) - pC * (xc - xB)) * idz2;
+                upd(k, oc + P * k, L, xc);
+                xB = xc;
+                xc = xT;
+                pC = cC;
+                pE = cE;
+                pW = cW;
+                pN = cN;
+                pS = cS;
+            }
+        }
+        if (k1 == g.nz + 1) wall(oc + P * g.nz);
     }
 }
 
@@ -478,35 +630,51 @@ __global__ __launch_bounds__(256) void k_cn_defect(Geo g, int kchunk, const floa
                                                    float* __restrict__ xo, double* __restrict__ uo, double h,
                                                    double inv_shift)
 {
+    // PHASE 0 applies the operator to R in FP64 arithmetic, the other phases
+    // to the FP32 iterate in FP32
+    using TC = std::conditional_t<PHASE == 0, double, float>;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
-    const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
-    const NuT<float, double> Nd{nut32, g, nu};
-    const NuT<float, float> Nf{nut32, g, (float)nu};
     const float h32 = (float)h, inv32 = (float)inv_shift;
     const int nplanes = COMP == 2 ? g.nz + 1 : g.nz;
     const int k0 = blockIdx.z * kchunk, k1 = min(nplanes, k0 + kchunk);
-    for (int k = k0; k < k1; ++k) {
-        const long long c = at(g, i, j, k);
-        if (COMP == 2 && (k == 0 || k == g.nz)) {
-            if (PHASE == 0) d0out[c] = 0.f;
-            if (PHASE < 2) xo[c] = 0.f;
-            else uo[c] = 0.0;
-            continue;
-        }
-        if (PHASE == 0) {
-            const float d = (float)(h * visc_apply<COMP, double>(g, Nd, R, c, i, j, k, im, ip, jm, jp));
+    auto upd = [&](int, long long c, TC L, TC xc) {
+        if constexpr (PHASE == 0) {
+            const float d = (float)(h * L);
             d0out[c] = d;
             xo[c] = d * inv32;
         } else {
-            const float xc = x[c];
-            const float L = visc_apply<COMP, float>(g, Nf, x, c, i, j, k, im, ip, jm, jp);
             const float xn = xc + (d0in[c] - xc + h32 * L) * inv32;
-            if (PHASE == 1) xo[c] = xn;
+            if constexpr (PHASE == 1) xo[c] = xn;
             else uo[c] = R[c] + (double)xn;
         }
-    }
+    };
+    auto wall = [&](long long c) {
+        if constexpr (PHASE == 0) d0out[c] = 0.f;
+        if constexpr (PHASE < 2) xo[c] = 0.f;
+        else uo[c] = 0.0;
+    };
+    if constexpr (PHASE == 0) visc_march<COMP, double>(g, i, j, k0, k1, nut32, nu, R, upd, wall);
+    else visc_march<COMP, float>(g, i, j, k0, k1, nut32, nu, x, upd, wall);
+}
+
+// One Crank-Nicolson iteration for component COMP:
+// x_out = x + (R - x + h L_nu x) * inv_shift, L_nu = d_j(nu_T d_j .).
+template <int COMP>
+__global__ __launch_bounds__(256) void k_cn(Geo g, int kchunk, const double* __restrict__ nut, double nu,
+                                            const double* __restrict__ R, const double* __restrict__ x,
+                                            double* __restrict__ xo, double h, double inv_shift)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const int nplanes = COMP == 2 ? g.nz + 1 : g.nz;
+    const int k0 = blockIdx.z * kchunk, k1 = min(nplanes, k0 + kchunk);
+    visc_march<COMP, double>(
+        g, i, j, k0, k1, nut, nu, x,
+        [&](int, long long c, double L, double xc) { xo[c] = xc + (R[c] - xc + h * L) * inv_shift; },
+        [&](long long c) { xo[c] = 0.0; });
 }
 
 __global__ void k_round32(float* __restrict__ d, const double* __restrict__ s, long long n)
