@@ -208,6 +208,24 @@ stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape
 /* The relaxation cycle in use: writes min(cap, M) weights, *m = M. */
 stp_status stp_schedule(const stp_ctx* ctx, double* omega, int32_t cap, int32_t* m);
 
+/* ---- checkpoint and restart ----------------------------------------------------
+ * Not in the paper (it writes periodic dumps and describes no restart).  Apart
+ * from the caller-owned workspace, which holds every field and history array,
+ * a context's state is the number of steps taken (it also selects the
+ * Adams-Bashforth start-up and history slots) and the number of earlier
+ * pressures held for the extrapolated warm start.  A checkpoint is a copy of
+ * the workspace plus stp_get_state(); copying both into a context made with
+ * the same configuration and calling stp_set_state() continues the run
+ * bitwise.  The network's workspace (weights) is not part of it. */
+typedef struct {
+    int32_t step;   /* steps completed */
+    int32_t nhist;  /* earlier solutions held for extrap_order (0..extrap_order) */
+} stp_state;
+
+stp_status stp_get_state(const stp_ctx* ctx, stp_state* out);
+/* STP_EINVAL if step < 0 or nhist lies outside 0..extrap_order. */
+stp_status stp_set_state(stp_ctx* ctx, const stp_state* in);
+
 /* ---- learned warm start ------------------------------------------------------
  * Not part of the paper: a 3-level 3-D convolutional network (16/32/64
  * channels, 3x3x3 kernels, ReLU, 2x average pooling, nearest upsampling with

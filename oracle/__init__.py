@@ -56,7 +56,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build_oracle())
+        # STP_ORACLE_LIB: another build of the same source (the sanitizer test)
+        _lib = ctypes.CDLL(os.environ.get("STP_ORACLE_LIB") or build_oracle())
         dp = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(Params)
         L = _lib

@@ -44,6 +44,10 @@ class SolveStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class State(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int32), ("nhist", ctypes.c_int32)]
+
+
 class StepStats(ctypes.Structure):
     _fields_ = [("poisson", SolveStats), ("step", ctypes.c_int32), ("cn_sweeps", ctypes.c_int32),
                 ("max_div", ctypes.c_double), ("u_bulk", ctypes.c_double), ("u_max", ctypes.c_double),
@@ -90,6 +94,10 @@ def load_library():
     L.stp_residual_norm.restype = i32
     L.stp_fields.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
     L.stp_fields.restype = i32
+    L.stp_get_state.argtypes = [vp, ctypes.POINTER(State)]
+    L.stp_get_state.restype = i32
+    L.stp_set_state.argtypes = [vp, ctypes.POINTER(State)]
+    L.stp_set_state.restype = i32
     L.stp_schedule.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
     L.stp_schedule.restype = i32
     L.stp_net_workspace_bytes.argtypes = [vp, i32]
@@ -162,6 +170,7 @@ class Channel:
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         self._ws_off = (-base) % 256
+        self._ws_bytes = nbytes
         h = ctypes.c_void_p()
         rc = self.lib.stp_init(ctypes.byref(cfg), ctypes.c_void_p(base + self._ws_off), nbytes, ctypes.byref(h))
         if rc != STP_OK:
@@ -186,6 +195,23 @@ class Channel:
         n = shape[0] * shape[1] * shape[2]
         off = ptr.value - self.workspace.data_ptr()
         return self.workspace[off:off + 8 * n].view(self.torch.float64).view(shape[0], shape[1], shape[2])
+
+    def checkpoint(self):
+        """(copy of the workspace, host state): everything stp_step advances."""
+        st = State()
+        self._check(self.lib.stp_get_state(self.handle, ctypes.byref(st)), "stp_get_state")
+        self.torch.cuda.current_stream(self.device).synchronize()
+        ws = self.workspace[self._ws_off:self._ws_off + self._ws_bytes].clone()
+        return ws, {"step": st.step, "nhist": st.nhist}
+
+    def restore(self, ck):
+        """Continue from checkpoint() of a context with the same configuration."""
+        ws, state = ck
+        if ws.numel() != self._ws_bytes:
+            raise StpError(STP_EINVAL, "checkpoint of another configuration")
+        self.workspace[self._ws_off:self._ws_off + self._ws_bytes].copy_(ws)
+        st = State(state["step"], state["nhist"])
+        self._check(self.lib.stp_set_state(self.handle, ctypes.byref(st)), "stp_set_state")
 
     def schedule(self):
         m = ctypes.c_int32()

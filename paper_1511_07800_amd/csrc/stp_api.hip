@@ -855,6 +855,22 @@ stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape
     return STP_OK;
 }
 
+stp_status stp_get_state(const stp_ctx* ctx, stp_state* out)
+{
+    if (!ctx || !out) return STP_EINVAL;
+    out->step = ctx->step;
+    out->nhist = ctx->nhist;
+    return STP_OK;
+}
+
+stp_status stp_set_state(stp_ctx* ctx, const stp_state* in)
+{
+    if (!ctx || !in || in->step < 0 || in->nhist < 0 || in->nhist > ctx->cfg.extrap_order) return STP_EINVAL;
+    ctx->step = in->step;
+    ctx->nhist = in->nhist;
+    return STP_OK;
+}
+
 stp_status stp_schedule(const stp_ctx* ctx, double* omega, int32_t cap, int32_t* m)
 {
     if (!ctx || !m || cap < 0 || (cap > 0 && !omega)) return STP_EINVAL;

@@ -92,11 +92,11 @@ def test_ctypes_structs_match_the_c_layout(tmp_path):
     import shutil
     import subprocess
     from paper_1511_07800_amd import Config
-    from paper_1511_07800_amd.binding import SolveStats, StepStats
+    from paper_1511_07800_amd.binding import SolveStats, StepStats, State
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    structs = {"stp_config": Config, "stp_solve_stats": SolveStats, "stp_step_stats": StepStats}
+    structs = {"stp_config": Config, "stp_solve_stats": SolveStats, "stp_step_stats": StepStats, "stp_state": State}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "stp.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

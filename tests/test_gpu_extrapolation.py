@@ -82,3 +82,27 @@ def test_extrapolation_keeps_tolerance_and_saves_sweeps(gpu, precision):
         # dt times the pressure difference
         assert err <= (1e-6 if name == "p" else 1e-8) * (100 if precision else 1), name
     assert sum(sweeps[2][-4:]) < sum(sweeps[0][-4:])
+
+
+def test_checkpoint_restore_continues_bitwise(gpu):
+    """k steps, a checkpoint (workspace copy and host state), k more steps;
+    a new context restored from the checkpoint takes the same k steps with
+    bitwise equal fields (mixed precision, extrapolated warm start, whose
+    history is part of the state)."""
+    import torch
+    from paper_1511_07800_amd import STP_U, STP_V, STP_W, STP_P
+    print("checkpoint/restore 128x64x64", flush=True)
+    ch = channel(2, precision=1, rtol=1e-8)
+    ch.step(4)
+    ck = ch.checkpoint()
+    assert ck[1] == {"step": 4, "nhist": 2}
+    ch.step(4)
+    ref = [ch.field(k).clone() for k in (STP_U, STP_V, STP_W, STP_P)]
+    ch.close()
+    ch2 = channel(2, precision=1, rtol=1e-8)
+    ch2.restore(ck)
+    st = ch2.step(4)
+    assert st["step"] == 8
+    for name, k, r in zip("uvwp", (STP_U, STP_V, STP_W, STP_P), ref):
+        assert torch.equal(ch2.field(k), r), name
+    ch2.close()
