@@ -171,3 +171,34 @@ def test_learned_warm_start_in_step(gpu):
         assert st["poisson"]["relres"] <= 1e-8
         assert st["learned_used"] == (st["relres_learned"] < st["relres_prev"])
         assert st["ms_net"] > 0
+
+
+def test_nan_weights_fall_back_to_plain_solve(gpu):
+    """A network with NaN weights: its warm start and its coarse corrections
+    are rejected by their residuals, and the steps equal those of the solver
+    without the network bit for bit (mixed precision)."""
+    import torch
+    from paper_1511_07800_amd import Channel, STP_WS_LEARNED, STP_WS_PREV, STP_MIXED
+    nx, ny, nz, lx, ly, lz = 32, 16, 16, 2 * math.pi, math.pi, 2.0
+    u, v, w = inputs.channel_state(nx, ny, nz, lz, 1 / 180, -1.0, noise=0.1, seed=41)
+    out = []
+    for learned in (False, True):
+        ch = Channel(nx, ny, nz, lx, ly, lz, nu=1 / 180, dpdx=-1.0, dt=2e-5, les=1, precision=STP_MIXED,
+                     warm_start=STP_WS_LEARNED if learned else STP_WS_PREV, learned_correction=int(learned),
+                     poisson_rtol=1e-8, poisson_maxit=100, srj_adaptive=1)
+        if learned:
+            ch.net_init(training=False, seed=3)
+            params, _ = ch.net_params()
+            params.fill_(float("nan"))
+            ch.net_sync()
+        load_state(ch, u, v, w)
+        for _ in range(3):
+            st = ch.step(1)
+            assert st["poisson"]["relres"] <= 1e-8
+            if learned:
+                assert st["learned_used"] == 0 and st["poisson"]["corrections"] == 0
+                assert not math.isfinite(st["relres_learned"])
+        out.append([ch.field(k).clone() for k in range(4)])
+        ch.close()
+    for name, a, b in zip("uvwp", out[0], out[1]):
+        assert torch.equal(a, b), name
