@@ -179,7 +179,7 @@ stp_status stp_step(stp_ctx* ctx, int32_t nsteps, stp_step_stats* last);
  * walls, periodic in x and y) with the context's schedule and precision.
  * With srj_adaptive = 1 each cycle is a Chebyshev/Leja cycle whose degree M
  * (rounded up to a multiple of 16) meets the bound 1/T_M <= rho on the residual
- * reduction, rho = max(rtol ||b|| / (2 ||r||), floor), floor = 1e-10 in FP64 and
+ * reduction, rho = max(rtol ||b|| / ||r||, floor), floor = 1e-10 in FP64 and
  * srj_reduction for the FP32 passes of the mixed mode; a cycle of degree M
  * multiplies every residual mode by at most 1/T_M, so one cycle usually meets
  * the test.

@@ -87,11 +87,11 @@ def schedule_of_degree(a, b, m):
 
 def adaptive_degree(a, b, rtol, bnorm, rnorm, floor):
     """Cycle degree for a pass that must reduce the residual from rnorm to
-    rtol * bnorm: rho = max(rtol bnorm / (2 rnorm), floor) capped at 1/2; the
+    rtol * bnorm: rho = max(rtol bnorm / rnorm, floor) capped at 1/2; the
     least degree with 1/T_M <= rho, rounded up to a multiple of 16.  (One
     cycle multiplies every residual mode by at most 1/T_M, so the 2-norm of the
     residual shrinks by at least that factor.)"""
-    rho = min(0.5, max(floor, 0.5 * rtol * bnorm / rnorm))
+    rho = min(0.5, max(floor, rtol * bnorm / rnorm))
     m = chebyshev_degree(a, b, rho)
     return (m + 15) // 16 * 16
 

@@ -258,11 +258,13 @@ stp_status readback(stp_ctx* ctx)
 // ping-ponging between *cur and *other; on return *cur holds the iterate.
 // The cycle for the next pass: the fixed cycle, or (adaptive) the Chebyshev/
 // Leja cycle whose degree, rounded up to a multiple of 16, bounds the residual
-// reduction by rho = max(rtol ||b|| / (2 ||r||), floor), rho <= 1/2.
+// reduction by rho = max(rtol ||b|| / ||r||, floor), rho <= 1/2: the residual
+// is mean-free, so each of its modes has kappa in [kmin, kmax] and is scaled
+// by at most 1/T_M, and one cycle meets the reduction still needed.
 const std::vector<double>& next_cycle(stp_ctx* ctx, double rtol, double fb, double rn, double floor_rho)
 {
     if (!ctx->cfg.srj_adaptive || !(rtol > 0.0) || !(rn > 0.0)) return ctx->omega;
-    double rho = 0.5 * rtol * fb / rn;
+    double rho = rtol * fb / rn;
     rho = std::min(0.5, std::max(floor_rho, rho));
     int m = chebyshev_degree(ctx->kmin, ctx->kmax, rho);
     m = (m + 15) / 16 * 16;

@@ -84,10 +84,45 @@ struct LapGeo {
     int nx, ny, nz;
     double idx2, idy2, idz2;
 };
-__device__ __forceinline__ double lap_at(const LapGeo& G, const double* __restrict__ p, long long v)
+// Cell coordinates along a grid-stride loop: divisions once per thread,
+// then the stride is added with carries (x fastest).
+struct CellIter {
+    long long v;
+    int x, y, z;
+    int sx, sy;
+    long long sz;
+    __device__ CellIter(const LapGeo& G, long long v0, long long stride) : v(v0)
+    {
+        const long long plane = (long long)G.nx * G.ny;
+        x = (int)(v0 % G.nx);
+        y = (int)((v0 / G.nx) % G.ny);
+        z = (int)(v0 / plane);
+        sx = (int)(stride % G.nx);
+        sy = (int)((stride / G.nx) % G.ny);
+        sz = stride / plane;
+    }
+    __device__ void advance(const LapGeo& G, long long stride)
+    {
+        v += stride;
+        x += sx;
+        int carry = 0;
+        if (x >= G.nx) {
+            x -= G.nx;
+            carry = 1;
+        }
+        y += sy + carry;
+        carry = 0;
+        if (y >= G.ny) {
+            y -= G.ny;
+            carry = 1;
+        }
+        z += (int)sz + carry;
+    }
+};
+
+__device__ __forceinline__ double lap_at(const LapGeo& G, const double* __restrict__ p, long long v, int x, int y, int z)
 {
     const long long plane = (long long)G.nx * G.ny;
-    const int x = (int)(v % G.nx), y = (int)((v / G.nx) % G.ny), z = (int)(v / plane);
     const long long row = v - x, pl = v - (long long)y * G.nx - x;
     const double pc = p[v];
     const double pe = p[row + (x == G.nx - 1 ? 0 : x + 1)], pw = p[row + (x == 0 ? G.nx - 1 : x - 1)];
@@ -106,10 +141,12 @@ __global__ __launch_bounds__(256) void k_sumsq_pr(LapGeo G, const double* __rest
     __shared__ double lds[8];
     const double m = sc[0];
     double a = 0.0, c = 0.0;
-    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (CellIter it(G, blockIdx.x * (long long)blockDim.x + threadIdx.x, stride); it.v < n; it.advance(G, stride)) {
+        const long long v = it.v;
         const double d = p[v] - m;
         a += d * d;
-        const double e = (b[v] - lap_at(G, p, v)) * invD;
+        const double e = (b[v] - lap_at(G, p, v, it.x, it.y, it.z)) * invD;
         c += e * e;
     }
     a = block_sum(a, lds);
@@ -142,8 +179,10 @@ __global__ void k_normalise(LapGeo G, const double* __restrict__ b, const double
 {
     const double m = sc[0], sr = sc[1], sp = sc[3];
     typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
-        const unsigned c01 = f2bf((float)((b[v] - lap_at(G, p, v)) * invD / sr)) |
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (CellIter it(G, blockIdx.x * (long long)blockDim.x + threadIdx.x, stride); it.v < n; it.advance(G, stride)) {
+        const long long v = it.v;
+        const unsigned c01 = f2bf((float)((b[v] - lap_at(G, p, v, it.x, it.y, it.z)) * invD / sr)) |
                              ((unsigned)f2bf((float)((p[v] - m) / sp)) << 16);
         u32x4* o = reinterpret_cast<u32x4*>(X + v * xstride);
         o[0] = u32x4{c01, 0u, 0u, 0u};
