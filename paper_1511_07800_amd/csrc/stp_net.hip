@@ -57,7 +57,7 @@ __device__ double block_sum(double v, double* lds)
     return r;
 }
 
-constexpr int kRedBlocks = 512;
+constexpr int kRedBlocks = 2048;  // 8 workgroups per CU keep enough loads in flight
 
 // part[q * kRedBlocks + block] for q < 2: sums of f0(v), f1(v)
 __global__ __launch_bounds__(256) void k_sum_p(const double* __restrict__ p, long long n, double* __restrict__ part)
