@@ -8,7 +8,9 @@ with inputs already resident in HBM.  Prints one JSON line.
 value  = relaxation cell-updates per second over the whole timed steps
          (sweeps x cells / wall time of the steps, everything included).
 Also reported: LES steps/s for the mixed (FP32 sweeps, FP64 residual and
-defect correction) and plain FP64 solves at the same relative residual, the
+defect correction) and plain FP64 solves at the same relative residual, for
+the mixed solve started from the extrapolated, the least-squares and the
+learned initial guesses and their combinations, the
 fields of every variant against the FP64 run's after the same steps, the
 dominant kernel's roofline (FP32 relaxation sweep, HBM-bound), a table of
 back-to-back sweep rates for every fusion depth in FP32 and FP64 beside a
@@ -27,6 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "pressure-relax Gcell-updates/s + %HBM peak; LES steps/s, learned vs plain"
 FIXED_CYCLES = False  # set by --fixed-cycles: repeat the 1e-3 cycle instead of sizing cycles adaptively
+PROJ_DEPTH = 8  # earlier solutions in the least-squares initial guess
 
 
 def parse():
@@ -49,14 +52,14 @@ def parse():
     return ap.parse_args()
 
 
-def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap_order=0):
+def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap_order=0, proj_depth=0):
     import torch
     from paper_1511_07800_amd import Channel, inputs
     ch = Channel(wl["nx"], wl["ny"], wl["nz"], wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"],
                  dt=wl["dt"], les=wl["les"], cs=wl.get("cs", 0.1), vd_a=wl.get("vd_a", 25.0), precision=precision,
                  poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=0 if FIXED_CYCLES else 1,
                  srj_reduction=wl.get("srj_reduction", 1e-3), learned_correction=learned_correction,
-                 extrap_order=extrap_order)
+                 extrap_order=extrap_order, proj_depth=proj_depth)
     u, v, w = inputs.channel_state(wl["nx"], wl["ny"], wl["nz"], wl["lz"], wl["nu"], wl["dpdx"],
                                    noise=wl.get("noise", 0.0), seed=wl.get("seed", 0))
     for k, a in enumerate((u, v, w)):
@@ -87,6 +90,8 @@ def time_steps(ch, steps, warmup, label):
               f"max_div {st['max_div']:.1e}" + (f" corrections {st['poisson']['corrections']}"
                                                  if st['poisson']['corrections'] else "") +
               (f" extrap order {st['extrap_used']} guess {st['relres_extrap']:.2e}" if st['relres_extrap'] > 0 else "") +
+              (f" lsq rank {st['proj_rank']} guess {st['relres_proj']:.2e} used {st['proj_used']}"
+               if st['proj_rank'] > 0 else "") +
               (f" net {st['ms_net']:.1f} ms relres p^n {st['relres_prev']:.2e} "
                                                  f"guess {st['relres_learned']:.2e}" if st['ms_net'] > 0 else ""),
               flush=True)
@@ -269,6 +274,17 @@ def main():
     del ch
     torch.cuda.empty_cache()
 
+    # least-squares guess from the last 8 solutions
+    ch = make_channel(wl, STP_MIXED, args.rtol, proj_depth=PROJ_DEPTH)
+    t_ls, acc_ls, st_ls = time_steps(ch, args.steps, args.warmup, "lsq+mixed")
+    lsq = {"steps_per_s": round(args.steps / t_ls, 4), "ms_per_step": round(1e3 * t_ls / args.steps, 2),
+           "sweeps_per_step": acc_ls["sweeps"] / args.steps, "proj_depth": PROJ_DEPTH,
+           "relres_prev_last": st_ls["relres_prev"], "relres_lsq_last": st_ls["relres_proj"]}
+    f_lsq = fields_of(ch)
+    ch.close()
+    del ch
+    torch.cuda.empty_cache()
+
     fp64 = None
     f_fp64 = None
     errors = {}
@@ -278,6 +294,7 @@ def main():
         f_fp64 = fields_of(ch)
         errors["mixed"] = field_errors(f_mixed, f_fp64)
         errors["extrap+mixed"] = field_errors(f_extrap, f_fp64)
+        errors["lsq+mixed"] = field_errors(f_lsq, f_fp64)
         fp64 = {"steps_per_s": round(args.steps / t64, 4), "ms_per_step": round(1e3 * t64 / args.steps, 2),
                 "sweeps_per_step": acc64["sweeps"] / args.steps,
                 "gcell_updates_per_s": round(acc64["sweeps"] * n / t64 / 1e9, 2),
@@ -291,12 +308,14 @@ def main():
     learned_cc = None
     learned_ex = None
     learned_all = None
+    learned_ls = None
+    learned_ls_cc = None
     if not args.no_learned:
         from paper_1511_07800_amd import STP_WS_LEARNED, warmstart
 
-        def run_learned(weights, label, correction=0, extrap_order=0):
+        def run_learned(weights, label, correction=0, extrap_order=0, proj_depth=0):
             ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED, learned_correction=correction,
-                              extrap_order=extrap_order)
+                              extrap_order=extrap_order, proj_depth=proj_depth)
             ch.net_init(training=False)
             warmstart.load_weights(ch, weights)
             tl, accl, stl = time_steps(ch, args.steps, args.warmup, label)
@@ -304,6 +323,7 @@ def main():
                    "sweeps_per_step": accl["sweeps"] / args.steps, "ms_net_last": round(stl["ms_net"], 2),
                    "relres_prev_last": stl["relres_prev"], "relres_learned_last": stl["relres_learned"],
                    "relres_extrap_last": stl["relres_extrap"] if extrap_order else None,
+                   "relres_lsq_last": stl["relres_proj"] if proj_depth else None,
                    "corrections_per_step": accl["corrections"] / args.steps,
                    "weights": os.path.relpath(weights, ROOT)}
             if f_fp64 is not None:
@@ -319,10 +339,13 @@ def main():
         learned_ex = run_learned(os.path.join(wdir, args.weights), "learned+extrap+mixed", extrap_order=2)
         learned_all = run_learned(os.path.join(wdir, args.weights), "learned+extrap+correction+mixed",
                                   correction=1, extrap_order=2)
+        learned_ls = run_learned(os.path.join(wdir, args.weights), "learned+lsq+mixed", proj_depth=PROJ_DEPTH)
+        learned_ls_cc = run_learned(os.path.join(wdir, args.weights), "learned+lsq+correction+mixed",
+                                    correction=1, proj_depth=PROJ_DEPTH)
 
     roof = roofline_from_steps(n, acc_mixed, 4, "k_relax_fused<float,4,8>")
     roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
-    del f_mixed, f_extrap, f_fp64
+    del f_mixed, f_extrap, f_lsq, f_fp64
     torch.cuda.empty_cache()
     table = None if args.no_table else relax_sweep_table(wl)
     cpu = None if args.no_cpu else cpu_baseline(wl)
@@ -338,24 +361,33 @@ def main():
                    "srj_cycles": "fixed 1e-3" if FIXED_CYCLES else "adaptive"},
         "les_steps_per_s": {"mixed": round(args.steps / t_mixed, 4), "fp64": fp64["steps_per_s"] if fp64 else None,
                             "extrap_mixed": extrap["steps_per_s"],
+                            "lsq_mixed": lsq["steps_per_s"],
                             "learned_mixed": learned["steps_per_s"] if learned else None,
                             "learned_mixed_correction": learned_cc["steps_per_s"] if learned_cc else None,
                             "learned_extrap_mixed": learned_ex["steps_per_s"] if learned_ex else None,
-                            "learned_extrap_mixed_correction": learned_all["steps_per_s"] if learned_all else None},
+                            "learned_extrap_mixed_correction": learned_all["steps_per_s"] if learned_all else None,
+                            "learned_lsq_mixed": learned_ls["steps_per_s"] if learned_ls else None,
+                            "learned_lsq_mixed_correction": learned_ls_cc["steps_per_s"] if learned_ls_cc else None},
         "sweeps_per_step": {"mixed": acc_mixed["sweeps"] / args.steps,
                             "fp64": fp64["sweeps_per_step"] if fp64 else None,
                             "extrap_mixed": extrap["sweeps_per_step"],
+                            "lsq_mixed": lsq["sweeps_per_step"],
                             "learned_mixed": learned["sweeps_per_step"] if learned else None,
                             "learned_mixed_correction": learned_cc["sweeps_per_step"] if learned_cc else None,
                             "learned_extrap_mixed": learned_ex["sweeps_per_step"] if learned_ex else None,
-                            "learned_extrap_mixed_correction": learned_all["sweeps_per_step"] if learned_all else None},
+                            "learned_extrap_mixed_correction": learned_all["sweeps_per_step"] if learned_all else None,
+                            "learned_lsq_mixed": learned_ls["sweeps_per_step"] if learned_ls else None,
+                            "learned_lsq_mixed_correction": learned_ls_cc["sweeps_per_step"] if learned_ls_cc else None},
         "fp64": fp64,
         "extrap_mixed": extrap,
+        "lsq_mixed": lsq,
         "learned_mixed": learned,
         "learned_mixed_trained_256x128x128": learned_256,
         "learned_mixed_correction": learned_cc,
         "learned_extrap_mixed": learned_ex,
         "learned_extrap_mixed_correction": learned_all,
+        "learned_lsq_mixed": learned_ls,
+        "learned_lsq_mixed_correction": learned_ls_cc,
         "error_vs_fp64": errors or None,
         "relax_sweeps": table,
         "roofline": roof,

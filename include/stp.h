@@ -122,6 +122,15 @@ typedef struct {
                                   (3 (p^n - p^{n-1}) + p^{n-2}), as far as earlier solutions exist; the
                                   learned warm start then refines that guess.  Needs STP_WS_PREV or
                                   STP_WS_LEARNED.  The stop test is unchanged. */
+    int32_t proj_depth;        /* Poisson initial guess by least squares over the last k = proj_depth
+                                  solutions (0: off; 1..8): x = sum_i c_i p^{n-i}, i = 0..k-1, with the c_i
+                                  minimising ||b - sum_i c_i b^{n-i}||_2 over the right-hand sides those
+                                  solutions were solved for (L p^{n-i} = b^{n-i} to the solve tolerance).
+                                  x is kept when its FP64 residual is below that of the other candidates
+                                  (p^n, the extrapolations); the learned warm start then refines the guess.
+                                  Only converged solves enter the history (a failed solve empties it).
+                                  Adds 2 proj_depth arrays of nx*ny*nz doubles to the workspace.  Needs
+                                  STP_WS_PREV or STP_WS_LEARNED.  The stop test is unchanged. */
     void* stream;              /* hipStream_t for all work */
 } stp_config;
 
@@ -156,6 +165,9 @@ typedef struct {
     int32_t extrap_used;   /* extrapolation order of the guess kept (0: p^n) */
     double ms_net;         /* network inference time, ms */
     double relres_extrap;  /* ... and of the extrapolated guess kept (0 when extrap_order = 0) */
+    double relres_proj;    /* ... and of the least-squares guess (0 when not formed) */
+    int32_t proj_used;     /* 1 if the solve started from the least-squares guess (or its refinement) */
+    int32_t proj_rank;     /* history columns the least-squares guess used (0 when not formed) */
 } stp_step_stats;
 
 /* Bytes of device workspace the configuration needs (0 if cfg is invalid). */
@@ -201,6 +213,19 @@ stp_status stp_relax(stp_ctx* ctx, int32_t dtype, const void* b_dev, void* p_dev
 /* ||b - L_p p||_2 in FP64 for FP64 device arrays (synchronises). */
 stp_status stp_residual_norm(stp_ctx* ctx, const void* b_dev, const void* p_dev, double* norm);
 
+/* The least-squares guess of proj_depth on caller-given histories (not in the
+ * paper; the paper starts each solve from the previous pressure, Sec. 3.4):
+ * out = sum_i c_i x_i with c minimising ||b - sum_i c_i y_i||_2, for k (1..8)
+ * earlier solutions x[i] and the right-hand sides y[i] they solve (newest
+ * first; the order only decides which of two dependent columns is dropped).
+ * x_dev and y_dev are host arrays of k device pointers; every array holds
+ * nx*ny*nz doubles and is borrowed.  Columns whose part orthogonal to the
+ * newer ones is below 1e-5 of their norm are left out; *rank receives the
+ * number used (0: out is not written).  STP_EINVAL for k outside 1..8 or a
+ * null pointer.  Synchronises. */
+stp_status stp_lsq_guess(stp_ctx* ctx, int32_t k, const void* const* x_dev, const void* const* y_dev,
+                         const void* b_dev, void* out_dev, int32_t* rank);
+
 /* Borrowed view of a field: device pointer, shape {nz or nz+1, ny, nx}
  * (slowest first) and dtype.  STP_W has nz+1 planes. */
 stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape[3], int32_t* dtype);
@@ -212,18 +237,21 @@ stp_status stp_schedule(const stp_ctx* ctx, double* omega, int32_t cap, int32_t*
  * Not in the paper (it writes periodic dumps and describes no restart).  Apart
  * from the caller-owned workspace, which holds every field and history array,
  * a context's state is the number of steps taken (it also selects the
- * Adams-Bashforth start-up and history slots) and the number of earlier
- * pressures held for the extrapolated warm start.  A checkpoint is a copy of
+ * Adams-Bashforth start-up and history slots, and the slots of the
+ * least-squares history) and the numbers of earlier solutions held for the
+ * extrapolated and the least-squares warm starts.  A checkpoint is a copy of
  * the workspace plus stp_get_state(); copying both into a context made with
  * the same configuration and calling stp_set_state() continues the run
  * bitwise.  The network's workspace (weights) is not part of it. */
 typedef struct {
     int32_t step;   /* steps completed */
     int32_t nhist;  /* earlier solutions held for extrap_order (0..extrap_order) */
+    int32_t nproj;  /* earlier solutions and right-hand sides held for proj_depth (0..proj_depth) */
 } stp_state;
 
 stp_status stp_get_state(const stp_ctx* ctx, stp_state* out);
-/* STP_EINVAL if step < 0 or nhist lies outside 0..extrap_order. */
+/* STP_EINVAL if step < 0, nhist lies outside 0..extrap_order or nproj outside
+ * 0..proj_depth. */
 stp_status stp_set_state(stp_ctx* ctx, const stp_state* in);
 
 /* ---- learned warm start ------------------------------------------------------

@@ -31,7 +31,7 @@ class Config(ctypes.Structure):
                 ("srj_reduction", ctypes.c_double), ("mixed_inner", ctypes.c_int32),
                 ("srj_adaptive", ctypes.c_int32), ("tblock", ctypes.c_int32),
                 ("cn_tol", ctypes.c_double), ("learned_correction", ctypes.c_int32), ("extrap_order", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("proj_depth", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class SolveStats(ctypes.Structure):
@@ -45,7 +45,7 @@ class SolveStats(ctypes.Structure):
 
 
 class State(ctypes.Structure):
-    _fields_ = [("step", ctypes.c_int32), ("nhist", ctypes.c_int32)]
+    _fields_ = [("step", ctypes.c_int32), ("nhist", ctypes.c_int32), ("nproj", ctypes.c_int32)]
 
 
 class StepStats(ctypes.Structure):
@@ -55,7 +55,8 @@ class StepStats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_poisson", ctypes.c_double),
                 ("relres_prev", ctypes.c_double), ("relres_learned", ctypes.c_double),
                 ("learned_used", ctypes.c_int32), ("extrap_used", ctypes.c_int32), ("ms_net", ctypes.c_double),
-                ("relres_extrap", ctypes.c_double)]
+                ("relres_extrap", ctypes.c_double), ("relres_proj", ctypes.c_double),
+                ("proj_used", ctypes.c_int32), ("proj_rank", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("poisson", "pad")}
@@ -92,6 +93,8 @@ def load_library():
     L.stp_relax.restype = i32
     L.stp_residual_norm.argtypes = [vp, vp, vp, ctypes.POINTER(dbl)]
     L.stp_residual_norm.restype = i32
+    L.stp_lsq_guess.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, ctypes.POINTER(i32)]
+    L.stp_lsq_guess.restype = i32
     L.stp_fields.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
     L.stp_fields.restype = i32
     L.stp_get_state.argtypes = [vp, ctypes.POINTER(State)]
@@ -136,7 +139,7 @@ class Channel:
     def __init__(self, nx, ny, nz, lx, ly, lz, nu, dpdx, dt, les=0, cs=0.1, vd_a=25.0,
                  precision=STP_FP64, warm_start=STP_WS_PREV, poisson_rtol=1e-10, poisson_maxit=1000,
                  omega=None, srj_reduction=1e-3, mixed_inner=1, tblock=4, cn_tol=1e-13, srj_adaptive=0,
-                 learned_correction=0, extrap_order=0,
+                 learned_correction=0, extrap_order=0, proj_depth=0,
                  device=None):
         import torch
         self.torch = torch
@@ -161,6 +164,7 @@ class Channel:
         cfg.srj_reduction, cfg.mixed_inner, cfg.tblock, cfg.cn_tol = srj_reduction, mixed_inner, tblock, cn_tol
         cfg.learned_correction = int(learned_correction)
         cfg.extrap_order = int(extrap_order)
+        cfg.proj_depth = int(proj_depth)
         cfg.srj_adaptive = srj_adaptive
         cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.cfg = cfg
@@ -202,7 +206,7 @@ class Channel:
         self._check(self.lib.stp_get_state(self.handle, ctypes.byref(st)), "stp_get_state")
         self.torch.cuda.current_stream(self.device).synchronize()
         ws = self.workspace[self._ws_off:self._ws_off + self._ws_bytes].clone()
-        return ws, {"step": st.step, "nhist": st.nhist}
+        return ws, {"step": st.step, "nhist": st.nhist, "nproj": st.nproj}
 
     def restore(self, ck):
         """Continue from checkpoint() of a context with the same configuration."""
@@ -210,7 +214,7 @@ class Channel:
         if ws.numel() != self._ws_bytes:
             raise StpError(STP_EINVAL, "checkpoint of another configuration")
         self.workspace[self._ws_off:self._ws_off + self._ws_bytes].copy_(ws)
-        st = State(state["step"], state["nhist"])
+        st = State(state["step"], state["nhist"], state.get("nproj", 0))
         self._check(self.lib.stp_set_state(self.handle, ctypes.byref(st)), "stp_set_state")
 
     def schedule(self):
@@ -248,6 +252,20 @@ class Channel:
         self._check(self.lib.stp_residual_norm(self.handle, _dptr(b), _dptr(p), ctypes.byref(out)),
                     "stp_residual_norm")
         return out.value
+
+    def lsq_guess(self, xs, ys, b, out):
+        """stp_lsq_guess: out = sum c_i xs[i] with c minimising ||b - sum c_i ys[i]||; returns the rank."""
+        t = self.torch
+        n = self.nx * self.ny * self.nz
+        for a in list(xs) + list(ys) + [b, out]:
+            assert a.dtype == t.float64 and a.is_contiguous() and a.numel() == n
+        k = len(xs)
+        xa = (ctypes.c_void_p * max(k, 1))(*[a.data_ptr() for a in xs])
+        ya = (ctypes.c_void_p * max(len(ys), 1))(*[a.data_ptr() for a in ys])
+        r = ctypes.c_int32()
+        self._check(self.lib.stp_lsq_guess(self.handle, k, xa, ya, _dptr(b), _dptr(out), ctypes.byref(r)),
+                    "stp_lsq_guess")
+        return r.value
 
     # -- learned warm start ---------------------------------------------------
     def net_init(self, training=True, seed=0):

@@ -27,6 +27,11 @@ struct stp_ctx {
     double* tmp = nullptr;  // Crank-Nicolson ping-pong partner (nw values)
     double *p1 = nullptr, *p2 = nullptr;  // p^{n-1}, p^{n-2} (extrapolated warm start)
     int nhist = 0;                        // of them, the solutions held
+    // least-squares history: the solution of step j and its right-hand side
+    // sit in slot j mod proj_depth; nproj of the latest steps are held
+    double* hp[kMaxProj] = {};
+    double* hb[kMaxProj] = {};
+    int nproj = 0;
     double* e[3][3] = {};   // Adams-Bashforth history, [slot][component]
     // FP32 work arrays of the mixed solve
     float *e0 = nullptr, *e1 = nullptr, *r32 = nullptr;
@@ -97,12 +102,15 @@ const char* validate(const stp_config& c)
     if (c.learned_correction != 0 && c.learned_correction != 1) return "learned_correction must be 0 or 1";
     if (c.extrap_order < 0 || c.extrap_order > 2) return "extrap_order must be 0, 1 or 2";
     if (c.extrap_order > 0 && c.warm_start == STP_WS_ZERO) return "extrap_order needs STP_WS_PREV or STP_WS_LEARNED";
+    if (c.proj_depth < 0 || c.proj_depth > kMaxProj) return "proj_depth must lie in 0..8";
+    if (c.proj_depth > 0 && c.warm_start == STP_WS_ZERO) return "proj_depth needs STP_WS_PREV or STP_WS_LEARNED";
     return nullptr;
 }
 
 // Byte offsets of every array in the workspace.
 struct Layout {
-    size_t u, v, w, p, ptmp, b, nut, rhs[3], tmp, p1, p2, e[3][3], e0, e1, r32, nut32, cnd, cna, cnb, part, res, total;
+    size_t u, v, w, p, ptmp, b, nut, rhs[3], tmp, p1, p2, hp[kMaxProj], hb[kMaxProj], e[3][3], e0, e1, r32, nut32,
+        cnd, cna, cnb, part, res, total;
 };
 
 Layout layout(const stp_config& c)
@@ -126,6 +134,10 @@ Layout layout(const stp_config& c)
     L.tmp = take(nw * 8);
     if (c.extrap_order >= 1) L.p1 = take(n * 8);
     if (c.extrap_order >= 2) L.p2 = take(n * 8);
+    for (int j = 0; j < c.proj_depth; ++j) {
+        L.hp[j] = take(n * 8);
+        L.hb[j] = take(n * 8);
+    }
     for (int sl = 0; sl < 3; ++sl)
         for (int q = 0; q < 3; ++q) L.e[sl][q] = take((q == 2 ? nw : n) * 8);
     L.e0 = take(n * 4);
@@ -452,6 +464,84 @@ stp_status solve(stp_ctx* ctx, const double* b, double* p, double rtol, int maxi
     return solve_fp64(ctx, b, p, ctx->ptmp, rtol, maxit, st);
 }
 
+// Coefficients a of the least-squares guess from the Gram quantities of
+// proj_gram (k(k+1)/2 entries <E_i, E_j>, i <= j row by row, then k entries
+// <E_i, b>): the normal equations M a = g, scaled to unit diagonal and solved
+// by a Cholesky factorisation that skips every E_i whose part orthogonal to
+// the columns kept before it is below kProjPivot of its norm squared (a
+// direction the history does not resolve).  Skipped columns get a = 0.
+// Returns the number of columns kept.
+constexpr long double kProjPivot = 1e-10L;
+
+int proj_coefficients(int k, const double* q, double* a)
+{
+    long double M[kMaxProj][kMaxProj], g[kMaxProj], sc[kMaxProj], L[kMaxProj][kMaxProj] = {}, z[kMaxProj];
+    int t = 0;
+    for (int i = 0; i < k; ++i)
+        for (int j = i; j < k; ++j) M[i][j] = M[j][i] = q[t++];
+    for (int i = 0; i < k; ++i) g[i] = q[t++];
+    bool keep[kMaxProj] = {};
+    for (int i = 0; i < k; ++i) {
+        a[i] = 0.0;
+        const long double d = M[i][i];
+        sc[i] = (std::isfinite((double)d) && d > 0.0L) ? 1.0L / std::sqrt(d) : 0.0L;
+    }
+    for (int i = 0; i < t; ++i)
+        if (!std::isfinite(q[i])) return 0;
+    int rank = 0;
+    for (int i = 0; i < k; ++i) {
+        if (sc[i] == 0.0L) continue;
+        long double d = 1.0L;
+        for (int j = 0; j < i; ++j) {
+            if (!keep[j]) continue;
+            long double v = M[i][j] * sc[i] * sc[j];
+            for (int m = 0; m < j; ++m)
+                if (keep[m]) v -= L[i][m] * L[j][m];
+            L[i][j] = v / L[j][j];
+            d -= L[i][j] * L[i][j];
+        }
+        if (!(d > kProjPivot)) continue;
+        L[i][i] = std::sqrt(d);
+        keep[i] = true;
+        ++rank;
+    }
+    if (rank == 0) return 0;
+    for (int i = 0; i < k; ++i) {  // L z = scaled g
+        if (!keep[i]) continue;
+        long double v = g[i] * sc[i];
+        for (int j = 0; j < i; ++j)
+            if (keep[j]) v -= L[i][j] * z[j];
+        z[i] = v / L[i][i];
+    }
+    for (int i = k - 1; i >= 0; --i) {  // L^T y = z, a = scaled y
+        if (!keep[i]) continue;
+        long double v = z[i];
+        for (int j = i + 1; j < k; ++j)
+            if (keep[j]) v -= L[j][i] * z[j];
+        z[i] = v / L[i][i];
+    }
+    for (int i = 0; i < k; ++i)
+        if (keep[i]) a[i] = (double)(z[i] * sc[i]);
+    for (int i = 0; i < k; ++i)
+        if (!std::isfinite(a[i])) return 0;
+    return rank;
+}
+
+// out = the least-squares guess from k held solutions xs and right-hand sides
+// ys (newest first) for the right-hand side b; *rank = columns used (out is
+// not written when 0).
+stp_status lsq_guess(stp_ctx* ctx, int k, const double* const* xs, const double* const* ys, const double* b,
+                     double* out, int* rank)
+{
+    stp_status rc;
+    CHK(proj_gram(k, ys, b, ctx->g.n, ctx->part, ctx->res, RES_PROJ, ctx->s));
+    if ((rc = readback(ctx)) != STP_OK) return rc;
+    double a[kMaxProj];
+    *rank = proj_coefficients(k, ctx->host + RES_PROJ, a);
+    if (*rank > 0) CHK(proj_combine(k, xs, a, out, ctx->g.n, ctx->s));
+    return STP_OK;
+}
+
 stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
 {
     const stp_config& c = ctx->cfg;
@@ -582,6 +672,38 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
         st.extrap_used = best;
         guess_res = rbest;
     }
+    if (c.proj_depth > 0 && ctx->nproj > 0) {
+        // least squares over the held solutions, newest first (slot of step j: j mod proj_depth)
+        if (guess_res < 0.0) {
+            CHK(residual(g, ctx->b, ctx->p, nullptr, ctx->part, ctx->res, s));
+            if ((rc = readback(ctx)) != STP_OK) return rc;
+            guess_res = std::sqrt(ctx->host[RES_R2]);
+            st.relres_prev = guess_res / std::max(std::sqrt(ctx->host[RES_B2]), 1e-300);
+        }
+        const int k = std::min(c.proj_depth, ctx->nproj);
+        const double* xs[kMaxProj];
+        const double* ys[kMaxProj];
+        for (int i = 0; i < k; ++i) {
+            const int slot = ((ctx->step - 1 - i) % c.proj_depth + c.proj_depth) % c.proj_depth;
+            xs[i] = ctx->hp[slot];
+            ys[i] = ctx->hb[slot];
+        }
+        int rank = 0;
+        if ((rc = lsq_guess(ctx, k, xs, ys, ctx->b, ctx->ptmp, &rank)) != STP_OK) return rc;
+        st.proj_rank = rank;
+        if (rank > 0) {
+            CHK(residual(g, ctx->b, ctx->ptmp, nullptr, ctx->part, ctx->res, s));
+            if ((rc = readback(ctx)) != STP_OK) return rc;
+            const double r = std::sqrt(ctx->host[RES_R2]);
+            st.relres_proj = r / std::max(std::sqrt(ctx->host[RES_B2]), 1e-300);
+            if (std::isfinite(r) && r < guess_res) {
+                CHK(copy(ctx->p, ctx->ptmp, g.n, s));
+                guess_res = r;
+                st.proj_used = 1;
+                st.extrap_used = 0;
+            }
+        }
+    }
     if (c.warm_start == STP_WS_LEARNED) {
         if (!ctx->net) {
             ctx->err = "STP_WS_LEARNED needs stp_net_init";
@@ -613,8 +735,22 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
         st.ms_net = msn;
     }
     CHK(hipEventRecord(ctx->ev[1], s));
-    if ((rc = solve(ctx, ctx->b, ctx->p, c.poisson_rtol, c.poisson_maxit, &st.poisson)) != STP_OK) return rc;
+    if ((rc = solve(ctx, ctx->b, ctx->p, c.poisson_rtol, c.poisson_maxit, &st.poisson)) != STP_OK) {
+        ctx->nproj = 0;
+        return rc;
+    }
     CHK(hipEventRecord(ctx->ev[2], s));
+    if (c.proj_depth > 0) {
+        // only converged solutions enter the least-squares history
+        if (st.poisson.status == STP_OK) {
+            const int slot = ctx->step % c.proj_depth;
+            CHK(copy(ctx->hp[slot], ctx->p, g.n, s));
+            CHK(copy(ctx->hb[slot], ctx->b, g.n, s));
+            ctx->nproj = std::min(ctx->nproj + 1, c.proj_depth);
+        } else {
+            ctx->nproj = 0;
+        }
+    }
 
     // 6. correction u = u* - dt grad p (Sec. 3.1)
     CHK(project(g, ctx->p, ctx->u, ctx->v, ctx->w, c.dt, s));
@@ -687,6 +823,10 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
     ctx->tmp = (double*)(base + L.tmp);
     if (c.extrap_order >= 1) ctx->p1 = (double*)(base + L.p1);
     if (c.extrap_order >= 2) ctx->p2 = (double*)(base + L.p2);
+    for (int j = 0; j < c.proj_depth; ++j) {
+        ctx->hp[j] = (double*)(base + L.hp[j]);
+        ctx->hb[j] = (double*)(base + L.hb[j]);
+    }
     for (int sl = 0; sl < 3; ++sl)
         for (int q = 0; q < 3; ++q) ctx->e[sl][q] = (double*)(base + L.e[sl][q]);
     ctx->e0 = (float*)(base + L.e0);
@@ -833,6 +973,33 @@ stp_status stp_residual_norm(stp_ctx* ctx, const void* b_dev, const void* p_dev,
     return STP_OK;
 }
 
+stp_status stp_lsq_guess(stp_ctx* ctx, int32_t k, const void* const* x_dev, const void* const* y_dev,
+                         const void* b_dev, void* out_dev, int32_t* rank)
+{
+    if (!ctx) return STP_EINVAL;
+    ctx->err.clear();
+    if (k < 1 || k > kMaxProj || !x_dev || !y_dev || !b_dev || !out_dev || !rank) {
+        ctx->err = "stp_lsq_guess: need 1 <= k <= 8 and non-null arrays";
+        return STP_EINVAL;
+    }
+    const double* xs[kMaxProj];
+    const double* ys[kMaxProj];
+    for (int i = 0; i < k; ++i) {
+        xs[i] = static_cast<const double*>(x_dev[i]);
+        ys[i] = static_cast<const double*>(y_dev[i]);
+        if (!xs[i] || !ys[i]) {
+            ctx->err = "stp_lsq_guess: null history array";
+            return STP_EINVAL;
+        }
+    }
+    int r = 0;
+    stp_status rc = lsq_guess(ctx, k, xs, ys, static_cast<const double*>(b_dev), static_cast<double*>(out_dev), &r);
+    if (rc != STP_OK) return rc;
+    *rank = r;
+    CHK(hipStreamSynchronize(ctx->s));
+    return STP_OK;
+}
+
 stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape[3], int32_t* dtype)
 {
     if (!ctx || !dev_ptr || !shape || !dtype) return STP_EINVAL;
@@ -862,14 +1029,18 @@ stp_status stp_get_state(const stp_ctx* ctx, stp_state* out)
     if (!ctx || !out) return STP_EINVAL;
     out->step = ctx->step;
     out->nhist = ctx->nhist;
+    out->nproj = ctx->nproj;
     return STP_OK;
 }
 
 stp_status stp_set_state(stp_ctx* ctx, const stp_state* in)
 {
-    if (!ctx || !in || in->step < 0 || in->nhist < 0 || in->nhist > ctx->cfg.extrap_order) return STP_EINVAL;
+    if (!ctx || !in || in->step < 0 || in->nhist < 0 || in->nhist > ctx->cfg.extrap_order || in->nproj < 0 ||
+        in->nproj > ctx->cfg.proj_depth)
+        return STP_EINVAL;
     ctx->step = in->step;
     ctx->nhist = in->nhist;
+    ctx->nproj = in->nproj;
     return STP_OK;
 }
 

@@ -36,11 +36,14 @@ enum ResSlot {
     RES_NUT_MAX = 4,
     RES_NET_LOSS = 5,
     RES_DIAG = 8,    // 5 values: max|div|, sum u, max|u|, max cfl, centreline sum
-    RES_COUNT = 16
+    RES_PROJ = 16,   // Gram matrix and right-hand side of the least-squares guess
+    RES_COUNT = 64
 };
 
 constexpr int kMaxPartBlocks = 65536;  // partial-sum slots per reduced quantity
 constexpr int kMaxFused = 5;           // sweeps fused per relaxation launch (FP64: 4)
+constexpr int kMaxProj = 8;            // earlier solutions in the least-squares guess
+static_assert(RES_PROJ + kMaxProj * (kMaxProj + 1) / 2 + kMaxProj <= RES_COUNT, "result slots");
 
 struct Weights {  // omega_s of the fused sweeps of one launch
     double omega[kMaxFused];
@@ -54,6 +57,15 @@ hipError_t copy(float* dst, const float* src, long long n, hipStream_t s);
 // out = 2p - p1 (order 1) or 3(p - p1) + p2 (order 2)
 hipError_t extrapolate(const double* p, const double* p1, const double* p2, int order, double* out, long long n,
                        hipStream_t s);
+// Least-squares guess from k <= kMaxProj earlier solutions x[0..k-1] and their
+// right-hand sides y[0..k-1] (newest first), both entering through their
+// backward differences at the newest, E_0 = y_0, E_j = sum_i (-1)^i C(j, i) y_i.
+// proj_gram writes <E_i, E_j> (i <= j, row by row) and then <E_i, b> into
+// res[slot ...]; proj_combine writes out = sum_j a[j] F_j with F the
+// differences of the x.
+hipError_t proj_gram(int k, const double* const* y, const double* b, long long n, double* part, double* res,
+                     int slot, hipStream_t s);
+hipError_t proj_combine(int k, const double* const* x, const double* a, double* out, long long n, hipStream_t s);
 hipError_t sumsq_into(const double* a, long long n, double* part, double* res, int slot, hipStream_t s);
 hipError_t zero_walls(const Geo& g, double* w, hipStream_t s);
 

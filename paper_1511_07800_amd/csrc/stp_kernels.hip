@@ -118,6 +118,97 @@ __global__ void k_extrapolate(const double* __restrict__ p, const double* __rest
         out[q] = order == 1 ? 2.0 * p[q] - p1[q] : 3.0 * (p[q] - p1[q]) + p2[q];
 }
 
+// ---- least-squares guess from earlier solutions ------------------------------
+// The right-hand sides y_0 (newest), y_1, ... of earlier steps and their
+// solutions x_0, x_1, ... enter through backward differences at the newest
+// (E_0 = y_0, E_j = sum_i (-1)^i C(j, i) y_i), formed per cell in registers.
+// Along a trajectory smooth in time the differences fall off by orders of
+// magnitude; in this basis, scaled to unit diagonal, the normal equations are
+// well conditioned where those of the raw vectors are not.
+
+struct HistPtrs {
+    const double* a[kMaxProj];
+};
+struct ProjCoef {
+    double a[kMaxProj];
+};
+
+// v[j] <- j-th backward difference at v[0], in place
+template <int K>
+__device__ __forceinline__ void backward_differences(double (&v)[K])
+{
+#pragma unroll
+    for (int j = 1; j < K; ++j)
+#pragma unroll
+        for (int i = K - 1; i >= j; --i) v[i] = v[i - 1] - v[i];
+}
+
+// Per-workgroup partial sums of <E_i, E_j> (i <= j, row by row) and then
+// <E_i, b>: NQ = K(K+1)/2 + K quantities, part[q * gridDim.x + block].
+template <int K>
+__global__ __launch_bounds__(256) void k_proj_gram(HistPtrs y, const double* __restrict__ b, long long n,
+                                                   double* __restrict__ part)
+{
+    constexpr int NQ = K * (K + 1) / 2 + K;
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+        double v[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) v[j] = y.a[j][c];
+        const double bc = b[c];
+        backward_differences<K>(v);
+        int q = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = i; j < K; ++j) acc[q++] += v[i] * v[j];
+#pragma unroll
+        for (int i = 0; i < K; ++i) acc[q++] += v[i] * bc;
+    }
+    __shared__ double lds[kBlock1d / 64][NQ];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double r = wave_reduce<false>(acc[q]);
+        if (lane == 0) lds[wave][q] = r;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < NQ; q += blockDim.x) {
+        double r = lds[0][q];
+        for (int w = 1; w < kBlock1d / 64; ++w) r += lds[w][q];
+        part[(long long)q * gridDim.x + blockIdx.x] = r;
+    }
+}
+
+// One workgroup per quantity: res[slot + q] = sum over blocks of part[q * nblk + block].
+__global__ __launch_bounds__(256) void k_finalize_each(const double* __restrict__ part, int nblk,
+                                                       double* __restrict__ res, int slot)
+{
+    __shared__ double lds[16];
+    const int q = blockIdx.x;
+    double v = 0.0;
+    for (int blk = threadIdx.x; blk < nblk; blk += blockDim.x) v += part[(long long)q * nblk + blk];
+    const double r = block_reduce<false>(v, lds);
+    if (threadIdx.x == 0) res[slot + q] = r;
+}
+
+template <int K>
+__global__ void k_proj_combine(HistPtrs x, ProjCoef a, double* __restrict__ out, long long n)
+{
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+        double v[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) v[j] = x.a[j][c];
+        backward_differences<K>(v);
+        double s = a.a[0] * v[0];
+#pragma unroll
+        for (int j = 1; j < K; ++j) s += a.a[j] * v[j];
+        out[c] = s;
+    }
+}
+
 __global__ void k_copy32(float* __restrict__ d, const float* __restrict__ s, long long n)
 {
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
@@ -852,6 +943,51 @@ hipError_t extrapolate(const double* p, const double* p1, const double* p2, int 
 hipError_t copy(float* dst, const float* src, long long n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_copy32, dim3(grid1d(n)), dim3(kBlock1d), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+hipError_t proj_gram(int k, const double* const* y, const double* b, long long n, double* part, double* res,
+                     int slot, hipStream_t s)
+{
+    if (k < 1 || k > kMaxProj) return hipErrorInvalidValue;
+    HistPtrs h{};
+    for (int j = 0; j < k; ++j) h.a[j] = y[j];
+    const int nb = grid1d(n, 1024);
+    const int nq = k * (k + 1) / 2 + k;
+    switch (k) {
+    case 1: hipLaunchKernelGGL(k_proj_gram<1>, dim3(nb), dim3(kBlock1d), 0, s, h, b, n, part); break;
+    case 2: hipLaunchKernelGGL(k_proj_gram<2>, dim3(nb), dim3(kBlock1d), 0, s, h, b, n, part); break;
+    case 3: hipLaunchKernelGGL(k_proj_gram<3>, dim3(nb), dim3(kBlock1d), 0, s, h, b, n, part); break;
+    case 4: hipLaunchKernelGGL(k_proj_gram<4>, dim3(nb), dim3(kBlock1d), 0, s, h, b, n, part); break;
+    case 5: hipLaunchKernelGGL(k_proj_gram<5>, dim3(nb), dim3(kBlock1d), 0, s, h, b, n, part); break;
+    case 6: hipLaunchKernelGGL(k_proj_gram<6>, dim3(nb), dim3(kBlock1d), 0, s, h, b, n, part); break;
+    case 7: hipLaunchKernelGGL(k_proj_gram<7>, dim3(nb), dim3(kBlock1d), 0, s, h, b, n, part); break;
+    default: hipLaunchKernelGGL(k_proj_gram<8>, dim3(nb), dim3(kBlock1d), 0, s, h, b, n, part); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finalize_each, dim3(nq), dim3(256), 0, s, part, nb, res, slot);
+    return hipGetLastError();
+}
+hipError_t proj_combine(int k, const double* const* x, const double* a, double* out, long long n, hipStream_t s)
+{
+    if (k < 1 || k > kMaxProj) return hipErrorInvalidValue;
+    HistPtrs h{};
+    ProjCoef c{};
+    for (int j = 0; j < k; ++j) {
+        h.a[j] = x[j];
+        c.a[j] = a[j];
+    }
+    const dim3 grid(grid1d(n)), block(kBlock1d);
+    switch (k) {
+    case 1: hipLaunchKernelGGL(k_proj_combine<1>, grid, block, 0, s, h, c, out, n); break;
+    case 2: hipLaunchKernelGGL(k_proj_combine<2>, grid, block, 0, s, h, c, out, n); break;
+    case 3: hipLaunchKernelGGL(k_proj_combine<3>, grid, block, 0, s, h, c, out, n); break;
+    case 4: hipLaunchKernelGGL(k_proj_combine<4>, grid, block, 0, s, h, c, out, n); break;
+    case 5: hipLaunchKernelGGL(k_proj_combine<5>, grid, block, 0, s, h, c, out, n); break;
+    case 6: hipLaunchKernelGGL(k_proj_combine<6>, grid, block, 0, s, h, c, out, n); break;
+    case 7: hipLaunchKernelGGL(k_proj_combine<7>, grid, block, 0, s, h, c, out, n); break;
+    default: hipLaunchKernelGGL(k_proj_combine<8>, grid, block, 0, s, h, c, out, n); break;
+    }
     return hipGetLastError();
 }
 hipError_t sumsq_into(const double* a, long long n, double* part, double* res, int slot, hipStream_t s)

@@ -59,10 +59,14 @@ def test_workspace_bytes_valid_and_invalid():
     # the extrapolated warm start keeps p^{n-1} (order 1) and p^{n-2} (order 2)
     for order in (1, 2):
         assert lib.stp_workspace_bytes(ctypes.byref(cfg(extrap_order=order))) == n_ok + order * 8 * n
+    # the least-squares guess keeps proj_depth solutions and their right-hand sides
+    for depth in (1, 8):
+        assert lib.stp_workspace_bytes(ctypes.byref(cfg(proj_depth=depth))) == n_ok + 2 * depth * 8 * n
     for bad in (dict(nz=1), dict(nx=0), dict(nu=0.0), dict(dt=-1.0), dict(lx=float("nan")),
                 dict(precision=7), dict(poisson_maxit=0), dict(poisson_rtol=-1.0), dict(srj_reduction=1.5),
                 dict(les=2), dict(tblock=-1), dict(tblock=6), dict(cn_tol=2.0), dict(srj_m=4),
-                dict(extrap_order=3), dict(extrap_order=1, warm_start=1)):
+                dict(extrap_order=3), dict(extrap_order=1, warm_start=1), dict(proj_depth=-1),
+                dict(proj_depth=9), dict(proj_depth=2, warm_start=1)):
         assert lib.stp_workspace_bytes(ctypes.byref(cfg(**bad))) == 0, bad
     assert lib.stp_workspace_bytes(None) == 0
 

@@ -95,7 +95,7 @@ def test_checkpoint_restore_continues_bitwise(gpu):
     ch = channel(2, precision=1, rtol=1e-8)
     ch.step(4)
     ck = ch.checkpoint()
-    assert ck[1] == {"step": 4, "nhist": 2}
+    assert ck[1] == {"step": 4, "nhist": 2, "nproj": 0}
     ch.step(4)
     ref = [ch.field(k).clone() for k in (STP_U, STP_V, STP_W, STP_P)]
     ch.close()

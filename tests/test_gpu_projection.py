@@ -1,0 +1,178 @@
+"""Least-squares warm start from earlier solutions, through the C ABI.
+
+stp_lsq_guess against the oracle (oracle/projection.py) on random and on
+polynomial-in-time histories, at a ragged size and at one spanning many
+workgroups; inside stp_step (proj_depth): the residual of the guess equals
+that of the oracle's guess from the same history (residual by the C oracle),
+the guess kept is the candidate of least residual, the solves still meet the
+tolerance, the fields agree with the run from p^n, fewer sweeps are needed,
+a checkpoint continues bitwise, and a failed solve empties the history."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import projection as pj
+from paper_1511_07800_amd import inputs
+from tests._helpers import rel_max
+
+pytestmark = pytest.mark.gpu
+
+G = dict(nx=128, ny=64, nz=64, lx=4 * math.pi, ly=2 * math.pi, lz=2.0, nu=1.0 / 180, dpdx=-1.0, dt=4e-5)
+
+
+def channel(proj_depth=0, extrap_order=0, precision=1, rtol=1e-8, g=G, maxit=200):
+    import torch
+    from paper_1511_07800_amd import Channel
+    ch = Channel(g["nx"], g["ny"], g["nz"], g["lx"], g["ly"], g["lz"], nu=g["nu"], dpdx=g["dpdx"], dt=g["dt"],
+                 les=1, precision=precision, poisson_rtol=rtol, poisson_maxit=maxit, srj_adaptive=1,
+                 srj_reduction=1e-4, extrap_order=extrap_order, proj_depth=proj_depth)
+    u, v, w = inputs.channel_state(g["nx"], g["ny"], g["nz"], g["lz"], g["nu"], g["dpdx"], noise=0.1, seed=7901)
+    for k, a in enumerate((u, v, w)):
+        ch.field(k).copy_(torch.from_numpy(a))
+    torch.cuda.synchronize()
+    return ch
+
+
+def taylor_history(rng, k, shape, t_new=1.0):
+    v = rng.standard_normal((k,) + shape)
+    vals = lambda t: sum(t ** m / math.factorial(m) * v[m] for m in range(k))  # noqa: E731
+    return [vals(-float(i)) for i in range(k)], vals(t_new)
+
+
+@pytest.mark.parametrize("dims", [(48, 20, 13), (128, 64, 64)])
+def test_lsq_guess_matches_oracle(gpu, dims):
+    import torch
+    nx, ny, nz = dims
+    print(f"stp_lsq_guess {nx}x{ny}x{nz}", flush=True)
+    ch = channel(g=dict(G, nx=nx, ny=ny, nz=nz))
+    shape = (nz, ny, nx)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    out = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    for k in range(1, 9):
+        rng = np.random.default_rng(500 + k)
+        # independent random columns
+        ys = [rng.standard_normal(shape) for _ in range(k)]
+        xs = [rng.standard_normal(shape) for _ in range(k)]
+        b = rng.standard_normal(shape)
+        x_o, c_o, r_o = pj.lsq_guess(b, xs, ys)
+        rank = ch.lsq_guess([dev(a) for a in xs], [dev(a) for a in ys], dev(b), out)
+        assert rank == k == r_o
+        err = rel_max(out.cpu().numpy(), x_o)
+        print(f"k={k} random: rel max err {err:.1e}", flush=True)
+        assert err <= 1e-10
+        # a polynomial in time of degree k - 1: the next value exactly
+        ys, b = taylor_history(rng, k, shape)
+        xs, x_new = taylor_history(rng, k, shape)
+        x_o, _, _ = pj.lsq_guess(b, xs, ys)
+        rank = ch.lsq_guess([dev(a) for a in xs], [dev(a) for a in ys], dev(b), out)
+        assert rank == k
+        e_new, e_o = rel_max(out.cpu().numpy(), x_new), rel_max(out.cpu().numpy(), x_o)
+        print(f"k={k} polynomial: vs exact {e_new:.1e}, vs oracle {e_o:.1e}", flush=True)
+        assert e_new <= 1e-7 and e_o <= 1e-7
+    # a repeated column is left out; the guess is the one without it
+    rng = np.random.default_rng(9)
+    ys = [rng.standard_normal(shape) for _ in range(2)]
+    xs = [rng.standard_normal(shape) for _ in range(2)]
+    b = rng.standard_normal(shape)
+    x_o, _, _ = pj.lsq_guess(b, xs, ys)
+    rank = ch.lsq_guess([dev(xs[0]), dev(xs[1]), dev(xs[0])], [dev(ys[0]), dev(ys[1]), dev(ys[0])], dev(b), out)
+    assert rank == 2
+    assert rel_max(out.cpu().numpy(), x_o) <= 1e-10
+    # argument checks on the host
+    from paper_1511_07800_amd import StpError
+    for k in (0, 9):
+        with pytest.raises(StpError):
+            ch.lsq_guess([out] * k, [out] * k, out, out)
+    ch.close()
+
+
+@pytest.mark.parametrize("depth", [3, 8])
+def test_step_guess_is_least_squares_and_least_residual(gpu, depth):
+    import torch
+    from paper_1511_07800_amd import STP_P, STP_RHS
+    print(f"least-squares guess in the step, depth {depth}", flush=True)
+    ch = channel(proj_depth=depth, extrap_order=2)
+    P = oracle.make_params(G["nx"], G["ny"], G["nz"], G["lx"], G["ly"], G["lz"])
+    xs, ys = [], []  # converged solutions and their right-hand sides, newest first
+    for n in range(depth + 3):
+        p_before = ch.field(STP_P).cpu().numpy().copy()
+        st = ch.step(1)
+        b = ch.field(STP_RHS).cpu().numpy().copy()
+        bn = np.linalg.norm(b)
+        assert st["poisson"]["relres"] <= 1e-8
+        r_prev = math.sqrt(oracle.residual(P, p_before, b)[1]) / bn
+        assert st["relres_prev"] == pytest.approx(r_prev, rel=1e-6)
+        k = min(depth, len(xs))
+        assert st["proj_rank"] == k
+        if k:
+            x_o, _, rank = pj.lsq_guess(b, xs[:k], ys[:k])
+            assert rank == k
+            r_o = math.sqrt(oracle.residual(P, x_o, b)[1]) / bn
+            print(f"step {n}: p^n {r_prev:.3e} extrap {st['relres_extrap']:.3e} lsq {st['relres_proj']:.3e} "
+                  f"oracle lsq {r_o:.3e} sweeps {st['poisson']['sweeps']}", flush=True)
+            assert st["relres_proj"] == pytest.approx(r_o, rel=0.02)
+        else:
+            assert st["relres_proj"] == 0.0 and st["proj_used"] == 0
+        cands = [r_prev] + ([st["relres_extrap"]] if st["relres_extrap"] > 0 else []) + \
+                ([st["relres_proj"]] if k else [])
+        assert st["poisson"]["relres0"] == pytest.approx(min(cands), rel=1e-9)
+        assert st["proj_used"] == (1 if k and st["relres_proj"] == min(cands) else 0)
+        xs.insert(0, ch.field(STP_P).cpu().numpy().copy())
+        ys.insert(0, b)
+    assert ch.checkpoint()[1]["nproj"] == depth
+    ch.close()
+
+
+def test_projection_keeps_tolerance_and_saves_sweeps(gpu):
+    import torch
+    from paper_1511_07800_amd import STP_U, STP_V, STP_W, STP_P
+    print("least-squares guess vs p^n and extrapolation, mixed", flush=True)
+    sweeps, out = {}, {}
+    for name, kw in (("prev", {}), ("extrap", dict(extrap_order=2)), ("lsq", dict(proj_depth=8))):
+        ch = channel(**kw)
+        sw = []
+        for _ in range(16):
+            st = ch.step(1)
+            assert st["poisson"]["relres"] <= 1e-8
+            sw.append(st["poisson"]["sweeps"])
+        sweeps[name] = sw
+        out[name] = [ch.field(k).clone() for k in (STP_U, STP_V, STP_W, STP_P)]
+        ch.close()
+    print("sweeps", sweeps, flush=True)
+    for fname, a, r in zip("uvwp", out["lsq"], out["prev"]):
+        err = float((a - r).norm() / r.norm())
+        print(fname, f"{err:.2e}", flush=True)
+        assert err <= (1e-6 if fname == "p" else 1e-8)
+    assert sum(sweeps["lsq"][-8:]) < sum(sweeps["extrap"][-8:]) < sum(sweeps["prev"][-8:])
+
+
+def test_checkpoint_restore_with_history_continues_bitwise(gpu):
+    import torch
+    from paper_1511_07800_amd import STP_U, STP_V, STP_W, STP_P
+    print("checkpoint/restore with least-squares history", flush=True)
+    ch = channel(proj_depth=4)
+    ch.step(6)
+    ck = ch.checkpoint()
+    assert ck[1] == {"step": 6, "nhist": 0, "nproj": 4}
+    ch.step(5)
+    ref = [ch.field(k).clone() for k in (STP_U, STP_V, STP_W, STP_P)]
+    ch.close()
+    ch2 = channel(proj_depth=4)
+    ch2.restore(ck)
+    st = ch2.step(5)
+    assert st["step"] == 11
+    for name, k, r in zip("uvwp", (STP_U, STP_V, STP_W, STP_P), ref):
+        assert torch.equal(ch2.field(k), r), name
+    ch2.close()
+
+
+def test_failed_solve_empties_history(gpu):
+    from paper_1511_07800_amd import STP_ENOCONV
+    print("failed solve resets the least-squares history", flush=True)
+    ch = channel(proj_depth=4, maxit=1, rtol=1e-14)
+    st = ch.step(1, allow=(STP_ENOCONV,))
+    assert st["poisson"]["status"] == STP_ENOCONV
+    assert ch.checkpoint()[1]["nproj"] == 0
+    ch.close()
