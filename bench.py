@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start run")
     ap.add_argument("--no-table", action="store_true", help="skip the sweep-rate table")
-    ap.add_argument("--weights", default="warmstart_les512_both.npy",
+    ap.add_argument("--weights", default="warmstart_les512_all.npy",
                     help="network weights of the learned variants (file in paper_1511_07800_amd/weights)")
     ap.add_argument("--fixed-cycles", action="store_true", help="repeat the fixed 1e-3 SRJ cycle (no adaptive sizing)")
     ap.add_argument("--sweeps", type=int, default=200, help="sweeps in the kernel roofline timing")

@@ -51,26 +51,50 @@ def extrapolated_base(ch, b, hist):
     return cands[min(range(len(r)), key=lambda i: r[i])]
 
 
+def lsq_base(ch, b, xs, ys):
+    """The library's least-squares guess (stp_lsq_guess) for b from the last
+    solutions xs and their right-hand sides ys, newest first; None if it
+    uses no column."""
+    import torch
+    out = torch.empty_like(b)
+    return out if ch.lsq_guess(xs, ys, b, out) > 0 else None
+
+
+LSQ_DEPTH = 8
+BASES = {"prev": ("prev",), "extrap": ("extrap",), "lsq": ("lsq",), "both": ("prev", "extrap"),
+         "all": ("prev", "extrap", "lsq")}
+
+
 def generate_pairs(ch, nsteps, every, skip=0, log=print, base="prev"):
     """Run nsteps time steps; after the first `skip`, keep every `every`-th
     step's (b, guess, p^{n+1}) as device tensors, with guess = p^n
-    (base "prev"), the extrapolated guess ("extrap"), or one triple of each
-    ("both", the extrapolated one only where it differs from p^n)."""
+    (base "prev"), the extrapolated guess ("extrap"), the least-squares guess
+    from the last 8 solutions ("lsq"), or one triple of each of p^n and the
+    extrapolated guess ("both") or of all three ("all"); a derived guess only
+    where it differs from p^n and, for "lsq", has the smaller residual."""
     pairs = []
+    kinds = BASES[base]
     hist = [ch.field(STP_P).clone()]
+    xs, ys = [], []  # solutions and their right-hand sides, newest first
     for n in range(nsteps):
         keep = n >= skip and (n - skip) % every == 0
         st = ch.step(1)
         p_next = ch.field(STP_P).clone()
+        b = ch.field(STP_RHS).clone()
         if keep:
-            b = ch.field(STP_RHS).clone()
-            if base in ("prev", "both"):
+            if "prev" in kinds:
                 pairs.append((b, hist[-1], p_next))
-            if base in ("extrap", "both"):
+            if "extrap" in kinds:
                 g = extrapolated_base(ch, b, hist)
                 if base == "extrap" or g is not hist[-1]:
                     pairs.append((b, g, p_next))
+            if "lsq" in kinds and xs:
+                g = lsq_base(ch, b, xs, ys)
+                if g is not None and ch.residual_norm(b, g) < ch.residual_norm(b, hist[-1]):
+                    pairs.append((b, g, p_next))
         hist = (hist + [p_next])[-3:]
+        if "lsq" in kinds:
+            xs, ys = [p_next] + xs[:LSQ_DEPTH - 1], [b] + ys[:LSQ_DEPTH - 1]
         if (n + 1) % 50 == 0:
             log(f"  data step {n + 1}/{nsteps}: sweeps {st['poisson']['sweeps']} relres0 "
                 f"{st['poisson']['relres0']:.2e} cfl {st['cfl']:.3f}")
@@ -152,8 +176,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--seed", type=int, default=None, help="noise seed of the data run (default: the workload's)")
-    ap.add_argument("--base", choices=("prev", "extrap", "both"), default="prev",
-                    help="guess the triples start from: p^n, the extrapolated guess, or both")
+    ap.add_argument("--base", choices=tuple(BASES), default="prev",
+                    help="guess the triples start from: p^n, the extrapolated or the least-squares guess, "
+                         "p^n and the extrapolated one (both), or all three (all)")
     ap.add_argument("--init", default=None, help="weights to start from (default: random initialisation)")
     args = ap.parse_args()
     import torch
