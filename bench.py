@@ -36,7 +36,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=8)
+    # untimed steps: past the start-up transient of the laminar+noise start and
+    # twice the least-squares history depth, so the timed steps are steady state
+    ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="les_channel_512x256x192")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
