@@ -724,7 +724,7 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
         const double r_net = std::sqrt(ctx->host[RES_R2]);
         const double bn = std::sqrt(ctx->host[RES_B2]);
         const double fb = bn > 1e-300 ? bn : 1e-300;
-        if (c.extrap_order == 0) st.relres_prev = r_prev / fb;
+        if (st.relres_prev == 0.0) st.relres_prev = r_prev / fb;  // not yet set by a candidate above
         st.relres_learned = r_net / fb;
         if (std::isfinite(r_net) && r_net < r_prev) {
             CHK(copy(ctx->p, ctx->ptmp, g.n, s));

@@ -176,3 +176,31 @@ def test_failed_solve_empties_history(gpu):
     assert st["poisson"]["status"] == STP_ENOCONV
     assert ch.checkpoint()[1]["nproj"] == 0
     ch.close()
+
+
+def test_learned_refinement_of_least_squares_guess_reports_p_n(gpu):
+    """With the network on top of the least-squares guess, relres_prev is the
+    residual of p^n (by the C oracle), relres_proj that of the least-squares
+    guess, and the solve starts from the least of the candidates."""
+    import torch
+    from paper_1511_07800_amd import Channel, STP_P, STP_RHS, STP_WS_LEARNED
+    g = dict(G, nx=64, ny=32, nz=32)
+    print("least-squares guess + network, 64x32x32", flush=True)
+    ch = Channel(g["nx"], g["ny"], g["nz"], g["lx"], g["ly"], g["lz"], nu=g["nu"], dpdx=g["dpdx"], dt=g["dt"],
+                 les=1, precision=1, poisson_rtol=1e-8, poisson_maxit=200, srj_adaptive=1, srj_reduction=1e-4,
+                 warm_start=STP_WS_LEARNED, proj_depth=3)
+    ch.net_init(training=False, seed=3)
+    u, v, w = inputs.channel_state(g["nx"], g["ny"], g["nz"], g["lz"], g["nu"], g["dpdx"], noise=0.1, seed=7902)
+    for k, a in enumerate((u, v, w)):
+        ch.field(k).copy_(torch.from_numpy(a))
+    P = oracle.make_params(g["nx"], g["ny"], g["nz"], g["lx"], g["ly"], g["lz"])
+    for n in range(5):
+        p_before = ch.field(STP_P).cpu().numpy().copy()
+        st = ch.step(1)
+        b = ch.field(STP_RHS).cpu().numpy().copy()
+        r_prev = math.sqrt(oracle.residual(P, p_before, b)[1]) / np.linalg.norm(b)
+        assert st["relres_prev"] == pytest.approx(r_prev, rel=1e-6)
+        cands = [r_prev, st["relres_learned"]] + ([st["relres_proj"]] if n else [])
+        assert st["poisson"]["relres0"] == pytest.approx(min(cands), rel=1e-9)
+        assert st["poisson"]["relres"] <= 1e-8
+    ch.close()
