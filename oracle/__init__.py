@@ -150,12 +150,9 @@ def poisson_srj(P, b, p0, omega, rtol, maxit):
     return p, st, cyc.value, r0.value, r1.value
 
 
-def poisson_srj_adaptive(P, b, p0, rtol, maxit, floor=1e-10, highpass=0.0):
+def poisson_srj_adaptive(P, b, p0, rtol, maxit, floor=1e-10):
     """SRJ solve whose every cycle is sized from the reduction still needed
-    (schedule.adaptive_degree); returns (p, status, cycles, sweeps, relres0, relres).
-    highpass = f > 0: the first cycle is the Chebyshev cycle on
-    [min(f kappa_min, kappa_max / 2), kappa_max] sized the same way on that
-    interval (a schedule choice of this implementation; the paper fixes none)."""
+    (schedule.adaptive_degree); returns (p, status, cycles, sweeps, relres0, relres)."""
     from .schedule import kappa_bounds as kb, adaptive_degree, schedule_of_degree
     a, bb = kb(P.nx, P.ny, P.nz, P.lx, P.ly, P.lz)
     p = np.array(p0, dtype=np.float64, order="C", copy=True)
@@ -172,8 +169,7 @@ def poisson_srj_adaptive(P, b, p0, rtol, maxit, floor=1e-10, highpass=0.0):
         if cycles >= maxit:
             status = -4
             break
-        lo = min(highpass * a, 0.5 * bb) if (highpass > 0.0 and cycles == 0) else a
-        om = schedule_of_degree(lo, bb, adaptive_degree(lo, bb, rtol, fb, rn, floor))
+        om = schedule_of_degree(a, bb, adaptive_degree(a, bb, rtol, fb, rn, floor))
         p, _, _, _, _ = poisson_srj(P, b, p, om, 0.0, 1)
         cycles += 1
         sweeps += len(om)

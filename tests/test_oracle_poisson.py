@@ -276,34 +276,3 @@ def test_adaptive_cycles_reach_tolerance_and_match_direct_solve():
     om = srj_schedule.srj_schedule(*g)
     _, _, cyc_f, _, _ = oracle.poisson_srj(P, b, np.zeros_like(b), om, 1e-10, 100)
     assert cyc_f * len(om) > sweeps
-
-
-def test_highpass_first_cycle_bounds_and_fallback():
-    """The high-pass first cycle (Chebyshev/Leja on [f kappa_min, kappa_max]):
-    its polynomial is at most 1 in magnitude below the interval (no mode is
-    amplified) and at most 1/T_M on it (closed form); from a start whose error
-    is rough one such cycle meets the tolerance, from a smooth one the
-    full-spectrum cycles that follow still reach it and the direct solution."""
-    g = (32, 16, 16, 2 * math.pi, math.pi, 2.0)
-    a, bb = srj_schedule.kappa_bounds(*g)
-    f = 64.0
-    lo = min(f * a, 0.5 * bb)
-    m = srj_schedule.adaptive_degree(lo, bb, 1e-8, 1.0, 1e-3, 1e-10)
-    om = srj_schedule.schedule_of_degree(lo, bb, m)
-    below = [abs(srj_schedule.cycle_factor(om, k)) for k in np.linspace(0.0, lo, 400)]
-    assert max(below) <= 1.0 + 1e-9
-    bound = 1.0 / math.cosh(m * math.acosh((bb + lo) / (bb - lo)))
-    inside = [abs(srj_schedule.cycle_factor(om, k)) for k in np.linspace(lo, bb, 3000)]
-    assert max(inside) <= bound * (1 + 1e-6)
-    P = oracle.make_params(*g)
-    b = inputs.poisson_rhs(32, 16, 16, seed=22)
-    ref = separable_direct_solve(g, b)
-    k, j, i = np.meshgrid(np.arange(16), np.arange(16), np.arange(32), indexing="ij")
-    rough = ref + 1e-3 * (-1.0) ** (i + j + k)
-    p, st, cyc, sweeps, r0, r1 = oracle.poisson_srj_adaptive(P, b, rough, 1e-8, 10, highpass=f)
-    m1 = srj_schedule.adaptive_degree(lo, bb, 1e-8, np.linalg.norm(b), r0 * np.linalg.norm(b), 1e-10)
-    assert st == 0 and cyc == 1 and sweeps == m1 and r1 <= 1e-8
-    smooth = ref + 1e-3 * np.cos(2 * math.pi * i / 32)
-    p, st, cyc, sweeps, r0, r1 = oracle.poisson_srj_adaptive(P, b, smooth, 1e-8, 10, highpass=f)
-    assert st == 0 and cyc >= 2 and r1 <= 1e-8
-    assert np.abs(p - ref).max() <= 1e-6 * np.abs(ref).max()
