@@ -177,13 +177,18 @@ def test_mixed_solve_against_fp64_oracle(gpu, g):
     assert err <= 1e-5
 
 
+FULL = {512: (512, 256, 192, 4 * math.pi, 2 * math.pi, 2.0), 1024: (1024, 512, 384, 4 * math.pi, 2 * math.pi, 2.0)}
+
+
+@pytest.mark.parametrize("size", [512, 1024])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_full_size_sweep_sampled(gpu, dtype):
-    """One sweep at the 512x256x192 LES grid in the benchmark's launch shape,
-    checked on 4096 sampled cells (walls, seams and interior) against the
-    oracle's pointwise formula."""
+def test_full_size_sweep_sampled(gpu, dtype, size):
+    """One sweep at the 512x256x192 LES grid and at the largest one
+    (1024x512x384, 2e8 cells), checked on about 4000 sampled cells (walls,
+    seams and interior) against the oracle's pointwise formula."""
     import torch
-    g = (512, 256, 192, 4 * math.pi, 2 * math.pi, 2.0)
+    g = FULL[size]
+    print(f"full-size sweep {g[:3]} {dtype}", flush=True)
     nx, ny, nz = g[:3]
     P = oracle.make_params(*g)
     r = inputs.rng(18)
@@ -232,15 +237,16 @@ def test_fused_sweeps_equal_single_sweeps_bitwise(gpu, g, dtype, nt):
     assert torch.equal(p1, pf)
 
 
-@pytest.mark.parametrize("dtype,nt", [("f32", 4), ("f32", 5), ("f64", 4)])
-def test_fused_sweeps_full_size_bitwise(gpu, dtype, nt):
+@pytest.mark.parametrize("dtype,nt,size", [("f32", 4, 512), ("f32", 5, 512), ("f64", 4, 512), ("f32", 4, 1024)])
+def test_fused_sweeps_full_size_bitwise(gpu, dtype, nt, size):
     """The fused launch at the benchmark grid (512x256x192, the launch
     configuration the bench times: several z-chunks per tile column, ragged
-    last tiles in x and y) equals single sweeps bit for bit; single sweeps at
-    this size are checked against the oracle in test_full_size_sweep_sampled."""
+    last tiles in x and y) and at the largest grid equals single sweeps bit
+    for bit; single sweeps at these sizes are checked against the oracle in
+    test_full_size_sweep_sampled."""
     import torch
-    g = (512, 256, 192, 4 * math.pi, 2 * math.pi, 2.0)
-    print(f"fused full size dtype={dtype} nt={nt}", flush=True)
+    g = FULL[size]
+    print(f"fused full size {g[:3]} dtype={dtype} nt={nt}", flush=True)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     r = inputs.rng(23)
     p = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
