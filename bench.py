@@ -81,7 +81,7 @@ def time_steps(ch, steps, warmup, label):
     for i in range(warmup):
         st = ch.step(1)
         print(f"[{label}] warmup step {i + 1}/{warmup}: sweeps {st['poisson']['sweeps']} "
-              f"relres0 {st['poisson']['relres0']:.2e} cfl {st['cfl']:.3f}", flush=True)
+              f"relres0 {st['poisson']['relres0']:.2e} cfl {st['cfl']:.3f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     acc = {"sweeps": 0, "launches": 0, "ms_relax": 0.0, "corrections": 0}
     t0 = time.perf_counter()
@@ -99,7 +99,7 @@ def time_steps(ch, steps, warmup, label):
                if st['proj_rank'] > 0 else "") +
               (f" net {st['ms_net']:.1f} ms relres p^n {st['relres_prev']:.2e} "
                                                  f"guess {st['relres_learned']:.2e}" if st['ms_net'] > 0 else ""),
-              flush=True)
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return dt, acc, st
@@ -156,7 +156,7 @@ def profile_kernels(wl):
         ch.relax(b, p, [om[k % len(om)] for k in range(8 * tb)])
         torch.cuda.synchronize()
         ch.close()
-    print("profile-kernels done", flush=True)
+    print("profile-kernels done", file=sys.stderr, flush=True)
 
 
 def relax_sweep_table(wl, timed=1020, warm=60):
