@@ -82,3 +82,42 @@ def test_training_from_scratch_improves_guess(gpu):
     print(f"held-out relres: p^n {rp:.3e}, untrained net {rn0:.3e}, trained net {rn:.3e}; loss {hist[0]:.3e} -> {hist[-1]:.3e}")
     assert hist[-1] < hist[0]
     assert rn < rp
+
+
+def test_network_gains_over_least_squares_guess_on_unseen_flow(gpu):
+    """The shipped 512x256x192 weights on the top of the least-squares guess
+    over the last 8 solutions, on a flow they have not seen (seed 9101):
+    after 16 warm-up steps, 8 steps each with and without the network, same
+    rtol 1e-8.  The network must lower the starting residual of the strongest
+    guess without it, and the sweeps."""
+    import os
+    wl = workloads.params("les_channel_512x256x192")
+    wts = os.path.join(os.path.dirname(warmstart.__file__), "weights", "warmstart_les512_all.npy")
+    res = {}
+    for ws in (STP_WS_PREV, STP_WS_LEARNED):
+        from paper_1511_07800_amd import Channel
+        ch = Channel(wl["nx"], wl["ny"], wl["nz"], wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"],
+                     dt=wl["dt"], les=1, precision=STP_MIXED, poisson_rtol=1e-8, poisson_maxit=200, srj_adaptive=1,
+                     srj_reduction=wl["srj_reduction"], warm_start=ws, proj_depth=8)
+        import torch
+        from paper_1511_07800_amd import inputs
+        u, v, w = inputs.channel_state(wl["nx"], wl["ny"], wl["nz"], wl["lz"], wl["nu"], wl["dpdx"],
+                                       noise=wl["noise"], seed=9101)
+        for k, a in enumerate((u, v, w)):
+            ch.field(k).copy_(torch.from_numpy(a))
+        if ws == STP_WS_LEARNED:
+            ch.net_init(training=False)
+            warmstart.load_weights(ch, wts)
+        ch.step(16)
+        sweeps, r0 = [], []
+        for _ in range(8):
+            st = ch.step(1)
+            assert st["poisson"]["relres"] <= 1e-8
+            assert st["proj_rank"] == 8
+            sweeps.append(st["poisson"]["sweeps"])
+            r0.append(st["poisson"]["relres0"])
+        res[ws] = dict(sweeps=np.mean(sweeps), relres0=np.exp(np.mean(np.log(r0))))
+        ch.close()
+    print("least squares vs least squares + network:", res)
+    assert res[STP_WS_LEARNED]["relres0"] < 0.5 * res[STP_WS_PREV]["relres0"]
+    assert res[STP_WS_LEARNED]["sweeps"] < res[STP_WS_PREV]["sweeps"]
