@@ -44,3 +44,24 @@ def fit_growth(ts, a, t0):
     growth = np.polyfit(ts[m], np.log(np.abs(a[m])), 1)[0]
     freq = np.polyfit(ts[m], np.unwrap(np.angle(a[m])), 1)[0]
     return growth, freq
+
+
+def ts_initial_state_paper(nx, ny, nz, lx, re, alpha, amplitude, n_cheb=100):
+    """The paper's scaling of its Orr-Sommerfeld validation (Sec. 4.1-4.2):
+    height 1, base flow U0 = Re z (1 - z), i.e. nu = 1/Re and G = -2, plus the
+    least stable mode with max |du| = amplitude * max U0.  Returns u, v, w,
+    lambda (in the paper's time unit), G and nu."""
+    nu, g, lz = 1.0 / re, -2.0, 1.0
+    u_, upp = os_solver.poiseuille_paper(re)
+    lam, c, psi, zc = os_solver.least_stable(alpha, re, u_, upp, 0.0, lz, n=n_cheb)
+    dx, dz = lx / nx, lz / nz
+    ze = np.arange(nz + 1) * dz
+    xe = np.arange(nx) * dx
+    ps = os_solver.eigenfunction(psi, zc, 0.0, lz, ze)
+    ps[0] = ps[-1] = 0.0
+    Psi = np.real(ps[:, None] * np.exp(1j * alpha * xe)[None, :])
+    du, dv, dw = inputs.faces_from_streamfunction(Psi, dx, dz, ny)
+    base = inputs.laminar_profile(nz, lz, nu, g)
+    amp = amplitude * np.abs(base).max() / np.abs(du).max()
+    u = base[:, None, None] + amp * du
+    return np.ascontiguousarray(u), amp * dv, np.ascontiguousarray(amp * dw), lam, g, nu
