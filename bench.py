@@ -57,14 +57,15 @@ def parse():
     return ap.parse_args()
 
 
-def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap_order=0, proj_depth=0):
+def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap_order=0, proj_depth=0,
+                 rhs16=0):
     import torch
     from paper_1511_07800_amd import Channel, inputs
     ch = Channel(wl["nx"], wl["ny"], wl["nz"], wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"],
                  dt=wl["dt"], les=wl["les"], cs=wl.get("cs", 0.1), vd_a=wl.get("vd_a", 25.0), precision=precision,
                  poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=0 if FIXED_CYCLES else 1,
                  srj_reduction=wl.get("srj_reduction", 1e-3), learned_correction=learned_correction,
-                 extrap_order=extrap_order, proj_depth=proj_depth)
+                 extrap_order=extrap_order, proj_depth=proj_depth, mixed_rhs16=rhs16)
     u, v, w = inputs.channel_state(wl["nx"], wl["ny"], wl["nz"], wl["lz"], wl["nu"], wl["dpdx"],
                                    noise=wl.get("noise", 0.0), seed=wl.get("seed", 0))
     for k, a in enumerate((u, v, w)):
@@ -105,17 +106,19 @@ def time_steps(ch, steps, warmup, label):
     return dt, acc, st
 
 
-def roofline_from_steps(n, acc, word_bytes, kernel):
+def roofline_from_steps(n, acc, word_bytes, kernel, rhs_bytes=None):
     """Roofline of the dominant kernel from the timed steps: one launch moves
-    3 words per cell of compulsory traffic (read p, read b, write p), so
-    achieved = 3 w n launches / device time of the sweep sequences."""
+    3 words per cell of compulsory traffic (read p, read b, write p; b takes
+    rhs_bytes when stored narrower), so achieved = that per cell x n x
+    launches / device time of the sweep sequences."""
     sec = acc["ms_relax"] * 1e-3
-    achieved = 3.0 * word_bytes * n * acc["launches"] / sec / 1e9
+    per_cell = 2.0 * word_bytes + (word_bytes if rhs_bytes is None else rhs_bytes)
+    achieved = per_cell * n * acc["launches"] / sec / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
             "launches": acc["launches"], "sweeps": acc["sweeps"],
             "us_per_launch": round(1e6 * sec / acc["launches"], 2),
-            "effective_GBs": round(3.0 * word_bytes * n * acc["sweeps"] / sec / 1e9, 1),
+            "effective_GBs": round(per_cell * n * acc["sweeps"] / sec / 1e9, 1),
             "gcell_updates_per_s": round(n * acc["sweeps"] / sec / 1e9, 1)}
 
 
@@ -300,6 +303,20 @@ def main():
     del ch
     torch.cuda.empty_cache()
 
+    # the mixed solve with each pass's right-hand side stored in FP16, from p^n and from the least-squares guess
+    def run_rhs16(label, **kw):
+        ch = make_channel(wl, STP_MIXED, args.rtol, rhs16=1, **kw)
+        t, acc, st = time_steps(ch, args.steps, args.warmup, label)
+        out = {"steps_per_s": round(args.steps / t, 4), "ms_per_step": round(1e3 * t / args.steps, 2),
+               "sweeps_per_step": acc["sweeps"] / args.steps, "outer_last": st["poisson"]["outer"],
+               "relax_kernel": roofline_from_steps(n, acc, 4, "k_relax_fused<float,_Float16,4,8>", rhs_bytes=2)}
+        f = fields_of(ch)
+        ch.close()
+        torch.cuda.empty_cache()
+        return out, f
+    mixed16, f_mixed16 = run_rhs16("mixed(rhs16)")
+    lsq16, f_lsq16 = run_rhs16("lsq+mixed(rhs16)", proj_depth=PROJ_DEPTH)
+
     fp64 = None
     f_fp64 = None
     errors = {}
@@ -310,6 +327,8 @@ def main():
         errors["mixed"] = field_errors(f_mixed, f_fp64)
         errors["extrap+mixed"] = field_errors(f_extrap, f_fp64)
         errors["lsq+mixed"] = field_errors(f_lsq, f_fp64)
+        errors["mixed(rhs16)"] = field_errors(f_mixed16, f_fp64)
+        errors["lsq+mixed(rhs16)"] = field_errors(f_lsq16, f_fp64)
         fp64 = {"steps_per_s": round(args.steps / t64, 4), "ms_per_step": round(1e3 * t64 / args.steps, 2),
                 "sweeps_per_step": acc64["sweeps"] / args.steps,
                 "gcell_updates_per_s": round(acc64["sweeps"] * n / t64 / 1e9, 2),
@@ -325,12 +344,13 @@ def main():
     learned_all = None
     learned_ls = None
     learned_ls_cc = None
+    learned_ls16 = None
     if not args.no_learned:
         from paper_1511_07800_amd import STP_WS_LEARNED, warmstart
 
-        def run_learned(weights, label, correction=0, extrap_order=0, proj_depth=0):
+        def run_learned(weights, label, correction=0, extrap_order=0, proj_depth=0, rhs16=0):
             ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED, learned_correction=correction,
-                              extrap_order=extrap_order, proj_depth=proj_depth)
+                              extrap_order=extrap_order, proj_depth=proj_depth, rhs16=rhs16)
             ch.net_init(training=False)
             warmstart.load_weights(ch, weights)
             tl, accl, stl = time_steps(ch, args.steps, args.warmup, label)
@@ -357,10 +377,12 @@ def main():
         learned_ls = run_learned(os.path.join(wdir, args.weights), "learned+lsq+mixed", proj_depth=PROJ_DEPTH)
         learned_ls_cc = run_learned(os.path.join(wdir, args.weights), "learned+lsq+correction+mixed",
                                     correction=1, proj_depth=PROJ_DEPTH)
+        learned_ls16 = run_learned(os.path.join(wdir, args.weights), "learned+lsq+mixed(rhs16)",
+                                   proj_depth=PROJ_DEPTH, rhs16=1)
 
     roof = roofline_from_steps(n, acc_mixed, 4, "k_relax_fused<float,4,8>")
     roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
-    del f_mixed, f_extrap, f_lsq, f_fp64
+    del f_mixed, f_extrap, f_lsq, f_mixed16, f_lsq16, f_fp64
     torch.cuda.empty_cache()
     table = None if args.no_table else relax_sweep_table(wl)
     cpu = None if args.no_cpu else cpu_baseline(wl)
@@ -377,25 +399,33 @@ def main():
         "les_steps_per_s": {"mixed": round(args.steps / t_mixed, 4), "fp64": fp64["steps_per_s"] if fp64 else None,
                             "extrap_mixed": extrap["steps_per_s"],
                             "lsq_mixed": lsq["steps_per_s"],
+                            "mixed_rhs16": mixed16["steps_per_s"],
+                            "lsq_mixed_rhs16": lsq16["steps_per_s"],
                             "learned_mixed": learned["steps_per_s"] if learned else None,
                             "learned_mixed_correction": learned_cc["steps_per_s"] if learned_cc else None,
                             "learned_extrap_mixed": learned_ex["steps_per_s"] if learned_ex else None,
                             "learned_extrap_mixed_correction": learned_all["steps_per_s"] if learned_all else None,
                             "learned_lsq_mixed": learned_ls["steps_per_s"] if learned_ls else None,
-                            "learned_lsq_mixed_correction": learned_ls_cc["steps_per_s"] if learned_ls_cc else None},
+                            "learned_lsq_mixed_correction": learned_ls_cc["steps_per_s"] if learned_ls_cc else None,
+                            "learned_lsq_mixed_rhs16": learned_ls16["steps_per_s"] if learned_ls16 else None},
         "sweeps_per_step": {"mixed": acc_mixed["sweeps"] / args.steps,
                             "fp64": fp64["sweeps_per_step"] if fp64 else None,
                             "extrap_mixed": extrap["sweeps_per_step"],
                             "lsq_mixed": lsq["sweeps_per_step"],
+                            "mixed_rhs16": mixed16["sweeps_per_step"],
+                            "lsq_mixed_rhs16": lsq16["sweeps_per_step"],
                             "learned_mixed": learned["sweeps_per_step"] if learned else None,
                             "learned_mixed_correction": learned_cc["sweeps_per_step"] if learned_cc else None,
                             "learned_extrap_mixed": learned_ex["sweeps_per_step"] if learned_ex else None,
                             "learned_extrap_mixed_correction": learned_all["sweeps_per_step"] if learned_all else None,
                             "learned_lsq_mixed": learned_ls["sweeps_per_step"] if learned_ls else None,
-                            "learned_lsq_mixed_correction": learned_ls_cc["sweeps_per_step"] if learned_ls_cc else None},
+                            "learned_lsq_mixed_correction": learned_ls_cc["sweeps_per_step"] if learned_ls_cc else None,
+                            "learned_lsq_mixed_rhs16": learned_ls16["sweeps_per_step"] if learned_ls16 else None},
         "fp64": fp64,
         "extrap_mixed": extrap,
         "lsq_mixed": lsq,
+        "mixed_rhs16": mixed16,
+        "lsq_mixed_rhs16": lsq16,
         "learned_mixed": learned,
         "learned_mixed_trained_256x128x128": learned_256,
         "learned_mixed_correction": learned_cc,
@@ -403,6 +433,7 @@ def main():
         "learned_extrap_mixed_correction": learned_all,
         "learned_lsq_mixed": learned_ls,
         "learned_lsq_mixed_correction": learned_ls_cc,
+        "learned_lsq_mixed_rhs16": learned_ls16,
         "error_vs_fp64": errors or None,
         "relax_sweeps": table,
         "roofline": roof,

@@ -87,7 +87,7 @@ typedef enum {
     STP_U = 0, STP_V = 1, STP_W = 2, STP_P = 3, STP_NUT = 4, STP_RHS = 5
 } stp_field;
 
-typedef enum { STP_DTYPE_F64 = 0, STP_DTYPE_F32 = 1 } stp_dtype;
+typedef enum { STP_DTYPE_F64 = 0, STP_DTYPE_F32 = 1, STP_DTYPE_F32_RHS16 = 2 } stp_dtype;
 
 typedef struct {
     int32_t nx, ny, nz;        /* cells; nx, ny >= 1, nz >= 2 */
@@ -131,6 +131,13 @@ typedef struct {
                                   Only converged solves enter the history (a failed solve empties it).
                                   Adds 2 proj_depth arrays of nx*ny*nz doubles to the workspace.  Needs
                                   STP_WS_PREV or STP_WS_LEARNED.  The stop test is unchanged. */
+    int32_t mixed_rhs16;       /* STP_MIXED only: 1 stores each FP32 pass's right-hand side (the FP64
+                                  residual) as FP16 after scaling it to unit rms, so the sweeps read 2
+                                  instead of 4 bytes of it per cell; the sweeps still compute in FP32
+                                  and the FP64 residual test is unchanged, but one pass then reduces
+                                  the residual by at most about 1e-3 (FP16 rounds each element to
+                                  within 4.9e-4), so the per-pass floor becomes max(srj_reduction,
+                                  1e-3).  Adds nx*ny*nz halves to the workspace.  0: FP32. */
     void* stream;              /* hipStream_t for all work */
 } stp_config;
 
@@ -205,7 +212,8 @@ stp_status stp_poisson_solve(stp_ctx* ctx, const void* b_dev, void* p_dev, doubl
 /* Apply an explicit list of Jacobi-SOR sweeps (Sec. 3.4):
  * p <- p + (omega_s / D)(L_p p - b) for s = 0..nsweeps-1, with
  * D = 2/dx^2 + 2/dy^2 + 2/dz^2.  dtype selects FP64 or FP32 arrays for
- * b_dev and p_dev (nx*ny*nz values each, borrowed).  omega is a host array.
+ * b_dev and p_dev (nx*ny*nz values each, borrowed), or STP_DTYPE_F32_RHS16:
+ * FP32 p with an FP16 b (widened exactly to FP32 on load).  omega is a host array.
  * Uses the context's fused-sweep setting.  Enqueues only; no sync. */
 stp_status stp_relax(stp_ctx* ctx, int32_t dtype, const void* b_dev, void* p_dev, const double* omega,
                      int32_t nsweeps);

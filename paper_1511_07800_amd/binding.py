@@ -9,7 +9,7 @@ STP_OK, STP_EINVAL, STP_ENOMEM, STP_EDEVICE, STP_ENOCONV, STP_ENAN = 0, -1, -2, 
 STP_FP64, STP_MIXED = 0, 1
 STP_WS_PREV, STP_WS_ZERO, STP_WS_LEARNED = 0, 1, 2
 STP_U, STP_V, STP_W, STP_P, STP_NUT, STP_RHS = range(6)
-STP_DTYPE_F64, STP_DTYPE_F32 = 0, 1
+STP_DTYPE_F64, STP_DTYPE_F32, STP_DTYPE_F32_RHS16 = 0, 1, 2
 
 _STATUS = {0: "STP_OK", -1: "STP_EINVAL", -2: "STP_ENOMEM", -3: "STP_EDEVICE", -4: "STP_ENOCONV", -5: "STP_ENAN"}
 
@@ -31,7 +31,7 @@ class Config(ctypes.Structure):
                 ("srj_reduction", ctypes.c_double), ("mixed_inner", ctypes.c_int32),
                 ("srj_adaptive", ctypes.c_int32), ("tblock", ctypes.c_int32),
                 ("cn_tol", ctypes.c_double), ("learned_correction", ctypes.c_int32), ("extrap_order", ctypes.c_int32),
-                ("proj_depth", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("proj_depth", ctypes.c_int32), ("mixed_rhs16", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class SolveStats(ctypes.Structure):
@@ -139,7 +139,7 @@ class Channel:
     def __init__(self, nx, ny, nz, lx, ly, lz, nu, dpdx, dt, les=0, cs=0.1, vd_a=25.0,
                  precision=STP_FP64, warm_start=STP_WS_PREV, poisson_rtol=1e-10, poisson_maxit=1000,
                  omega=None, srj_reduction=1e-3, mixed_inner=1, tblock=4, cn_tol=1e-13, srj_adaptive=0,
-                 learned_correction=0, extrap_order=0, proj_depth=0,
+                 learned_correction=0, extrap_order=0, proj_depth=0, mixed_rhs16=0,
                  device=None):
         import torch
         self.torch = torch
@@ -165,6 +165,7 @@ class Channel:
         cfg.learned_correction = int(learned_correction)
         cfg.extrap_order = int(extrap_order)
         cfg.proj_depth = int(proj_depth)
+        cfg.mixed_rhs16 = int(mixed_rhs16)
         cfg.srj_adaptive = srj_adaptive
         cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.cfg = cfg
@@ -241,9 +242,10 @@ class Channel:
 
     def relax(self, b, p, omega):
         t = self.torch
-        assert b.dtype == p.dtype and b.dtype in (t.float64, t.float32)
+        assert (b.dtype == p.dtype and b.dtype in (t.float64, t.float32)) or (b.dtype == t.float16 and
+                                                                              p.dtype == t.float32)
         assert b.is_contiguous() and p.is_contiguous() and b.numel() == p.numel() == self.nx * self.ny * self.nz
-        dtype = STP_DTYPE_F64 if b.dtype == t.float64 else STP_DTYPE_F32
+        dtype = {t.float64: STP_DTYPE_F64, t.float32: STP_DTYPE_F32, t.float16: STP_DTYPE_F32_RHS16}[b.dtype]
         arr = (ctypes.c_double * max(1, len(omega)))(*[float(x) for x in omega])
         self._check(self.lib.stp_relax(self.handle, dtype, _dptr(b), _dptr(p), arr, len(omega)), "stp_relax")
 

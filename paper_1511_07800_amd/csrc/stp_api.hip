@@ -35,6 +35,7 @@ struct stp_ctx {
     double* e[3][3] = {};   // Adams-Bashforth history, [slot][component]
     // FP32 work arrays of the mixed solve
     float *e0 = nullptr, *e1 = nullptr, *r32 = nullptr;
+    _Float16* r16 = nullptr;  // mixed_rhs16: scaled FP16 copy of r32
     // FP32 arrays of the mixed-mode Crank-Nicolson solve: nu_T, h L R, increments
     float *nut32 = nullptr, *cnd = nullptr, *cna = nullptr, *cnb = nullptr;
     double* part = nullptr;  // reduction partials
@@ -54,6 +55,9 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr double kCnTol32 = 1e-7;  // FP32 resolution of the Crank-Nicolson increment
+// least per-pass residual reduction asked of a pass whose right-hand side is
+// stored in FP16 (unit roundoff 2^-11 = 4.9e-4 on every element)
+constexpr double kRhs16Floor = 1e-3;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -104,13 +108,15 @@ const char* validate(const stp_config& c)
     if (c.extrap_order > 0 && c.warm_start == STP_WS_ZERO) return "extrap_order needs STP_WS_PREV or STP_WS_LEARNED";
     if (c.proj_depth < 0 || c.proj_depth > kMaxProj) return "proj_depth must lie in 0..8";
     if (c.proj_depth > 0 && c.warm_start == STP_WS_ZERO) return "proj_depth needs STP_WS_PREV or STP_WS_LEARNED";
+    if (c.mixed_rhs16 != 0 && c.mixed_rhs16 != 1) return "mixed_rhs16 must be 0 or 1";
+    if (c.mixed_rhs16 && c.precision != STP_MIXED) return "mixed_rhs16 needs STP_MIXED";
     return nullptr;
 }
 
 // Byte offsets of every array in the workspace.
 struct Layout {
-    size_t u, v, w, p, ptmp, b, nut, rhs[3], tmp, p1, p2, hp[kMaxProj], hb[kMaxProj], e[3][3], e0, e1, r32, nut32,
-        cnd, cna, cnb, part, res, total;
+    size_t u, v, w, p, ptmp, b, nut, rhs[3], tmp, p1, p2, hp[kMaxProj], hb[kMaxProj], e[3][3], e0, e1, r32, r16,
+        nut32, cnd, cna, cnb, part, res, total;
 };
 
 Layout layout(const stp_config& c)
@@ -143,6 +149,7 @@ Layout layout(const stp_config& c)
     L.e0 = take(n * 4);
     L.e1 = take(n * 4);
     L.r32 = take(n * 4);
+    if (c.precision == STP_MIXED && c.mixed_rhs16) L.r16 = take(n * 2);
     if (c.precision == STP_MIXED) {
         L.nut32 = take(n * 4);
         L.cnd = take(nw * 4);
@@ -285,8 +292,8 @@ const std::vector<double>& next_cycle(stp_ctx* ctx, double rtol, double fb, doub
     return it->second;
 }
 
-template <typename T>
-stp_status run_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, const double* omega, int m, long long first,
+template <typename T, typename TB = T>
+stp_status run_sweeps(stp_ctx* ctx, const TB* b, T** cur, T** other, const double* omega, int m, long long first,
                       long long count, int* launches = nullptr)
 {
     // tblock sweeps per launch where the grid allows it (FP64: at most 4),
@@ -297,7 +304,7 @@ stp_status run_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, const double
         const int nf = (int)std::min<long long>(tb, count - s);
         Weights wts{};
         for (int f = 0; f < nf; ++f) wts.omega[f] = omega[(first + s + f) % m];
-        CHK(relax<T>(ctx->g, b, *cur, *other, wts, nf, ctx->s));
+        CHK(relax(ctx->g, b, (const T*)*cur, *other, wts, nf, ctx->s));
         std::swap(*cur, *other);
         s += nf;
         if (launches) ++*launches;
@@ -307,12 +314,12 @@ stp_status run_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, const double
 
 // run_sweeps between two events; adds the device time to st->ms_relax after
 // the next synchronisation (timed_flush).
-template <typename T>
-stp_status timed_sweeps(stp_ctx* ctx, const T* b, T** cur, T** other, const std::vector<double>& omega, long long count,
+template <typename T, typename TB = T>
+stp_status timed_sweeps(stp_ctx* ctx, const TB* b, T** cur, T** other, const std::vector<double>& omega, long long count,
                         stp_solve_stats* st)
 {
     CHK(hipEventRecord(ctx->ev[4], ctx->s));
-    stp_status rc = run_sweeps<T>(ctx, b, cur, other, omega.data(), (int)omega.size(), 0, count, &st->launches);
+    stp_status rc = run_sweeps<T, TB>(ctx, b, cur, other, omega.data(), (int)omega.size(), 0, count, &st->launches);
     if (rc != STP_OK) return rc;
     CHK(hipEventRecord(ctx->ev[5], ctx->s));
     return STP_OK;
@@ -396,16 +403,29 @@ stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, in
     st->status = STP_OK;
     int outer = 0;
     long long sweeps = 0;
+    // with mixed_rhs16 the pass's right-hand side is an FP16 copy of the
+    // residual scaled to unit rms, which bounds what one pass can reduce
+    const bool rhs16 = ctx->cfg.mixed_rhs16 != 0;
+    const double floor_rho = rhs16 ? std::max(ctx->cfg.srj_reduction, kRhs16Floor) : ctx->cfg.srj_reduction;
     auto pass = [&]() -> stp_status {
         float* cur = ctx->e0;
         float* oth = ctx->e1;
         CHK(fill(cur, 0.0f, ctx->g.n, ctx->s));
-        const std::vector<double>& cyc = rtol > 0.0 ? next_cycle(ctx, rtol, fb, rn, ctx->cfg.srj_reduction) : ctx->omega;
+        const std::vector<double>& cyc = rtol > 0.0 ? next_cycle(ctx, rtol, fb, rn, floor_rho) : ctx->omega;
         const long long count = (long long)cyc.size() * inner;
         sweeps += count;
-        stp_status r2 = timed_sweeps<float>(ctx, ctx->r32, &cur, &oth, cyc, count, st);
-        if (r2 != STP_OK) return r2;
-        CHK(add_correction(p, cur, ctx->g.n, ctx->s));
+        stp_status r2;
+        if (rhs16 && rn > 0.0 && std::isfinite(rn)) {
+            const double scale = std::sqrt((double)ctx->g.n) / rn;
+            CHK(half_scaled(ctx->r16, ctx->r32, ctx->g.n, (float)scale, ctx->s));
+            r2 = timed_sweeps<float, _Float16>(ctx, ctx->r16, &cur, &oth, cyc, count, st);
+            if (r2 != STP_OK) return r2;
+            CHK(add_correction_scaled(p, cur, ctx->g.n, 1.0 / scale, ctx->s));
+        } else {
+            r2 = timed_sweeps<float>(ctx, ctx->r32, &cur, &oth, cyc, count, st);
+            if (r2 != STP_OK) return r2;
+            CHK(add_correction(p, cur, ctx->g.n, ctx->s));
+        }
         CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s));
         r2 = readback(ctx);
         if (r2 != STP_OK) return r2;
@@ -832,6 +852,7 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
     ctx->e0 = (float*)(base + L.e0);
     ctx->e1 = (float*)(base + L.e1);
     ctx->r32 = (float*)(base + L.r32);
+    if (c.precision == STP_MIXED && c.mixed_rhs16) ctx->r16 = (_Float16*)(base + L.r16);
     if (c.precision == STP_MIXED) {
         ctx->nut32 = (float*)(base + L.nut32);
         ctx->cnd = (float*)(base + L.cnd);
@@ -929,7 +950,8 @@ stp_status stp_relax(stp_ctx* ctx, int32_t dtype, const void* b_dev, void* p_dev
 {
     if (!ctx) return STP_EINVAL;
     ctx->err.clear();
-    if (!b_dev || !p_dev || nsweeps < 0 || (nsweeps > 0 && !omega) || (dtype != STP_DTYPE_F64 && dtype != STP_DTYPE_F32)) {
+    if (!b_dev || !p_dev || nsweeps < 0 || (nsweeps > 0 && !omega) ||
+        (dtype != STP_DTYPE_F64 && dtype != STP_DTYPE_F32 && dtype != STP_DTYPE_F32_RHS16)) {
         ctx->err = "stp_relax: bad argument";
         return STP_EINVAL;
     }
@@ -950,8 +972,12 @@ stp_status stp_relax(stp_ctx* ctx, int32_t dtype, const void* b_dev, void* p_dev
         float* p = static_cast<float*>(p_dev);
         float* cur = p;
         float* oth = ctx->e1;
-        if ((rc = run_sweeps<float>(ctx, static_cast<const float*>(b_dev), &cur, &oth, omega, nsweeps, 0, nsweeps)) != STP_OK)
-            return rc;
+        if (dtype == STP_DTYPE_F32)
+            rc = run_sweeps<float>(ctx, static_cast<const float*>(b_dev), &cur, &oth, omega, nsweeps, 0, nsweeps);
+        else
+            rc = run_sweeps<float, _Float16>(ctx, static_cast<const _Float16*>(b_dev), &cur, &oth, omega, nsweeps, 0,
+                                             nsweeps);
+        if (rc != STP_OK) return rc;
         if (cur != p) CHK(copy(p, cur, ctx->g.n, ctx->s));
     }
     return STP_OK;

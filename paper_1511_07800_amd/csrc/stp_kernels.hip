@@ -268,6 +268,21 @@ __global__ void k_add_correction(double* __restrict__ p, const float* __restrict
         p[q] += (double)e[q];
 }
 
+// p += e / scale: the correction of a pass whose right-hand side was scaled by `scale`
+__global__ void k_add_correction_scaled(double* __restrict__ p, const float* __restrict__ e, long long n,
+                                        double inv_scale)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        p[q] += inv_scale * (double)e[q];
+}
+
+// FP16 copy of scale * r (round to nearest); scale brings the rms of r to 1
+__global__ void k_half_scaled(_Float16* __restrict__ d, const float* __restrict__ r, long long n, float scale)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        d[q] = (_Float16)(scale * r[q]);
+}
+
 // ---- eddy viscosity (Sec. 2.2) ---------------------------------------------
 
 // nu_T = nu + (C_S Delta phi_w)^2 |S| at cell centres; phi_w = 1 - exp(-z+/A)
@@ -1106,6 +1121,16 @@ hipError_t residual(const Geo& g, const double* b, const double* p, float* r32, 
 hipError_t add_correction(double* p, const float* e, long long n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_add_correction, dim3(grid1d(n)), dim3(kBlock1d), 0, s, p, e, n);
+    return hipGetLastError();
+}
+hipError_t add_correction_scaled(double* p, const float* e, long long n, double inv_scale, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_correction_scaled, dim3(grid1d(n)), dim3(kBlock1d), 0, s, p, e, n, inv_scale);
+    return hipGetLastError();
+}
+hipError_t half_scaled(_Float16* dst, const float* r, long long n, float scale, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_half_scaled, dim3(grid1d(n)), dim3(kBlock1d), 0, s, dst, r, n, scale);
     return hipGetLastError();
 }
 

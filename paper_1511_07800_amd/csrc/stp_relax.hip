@@ -157,6 +157,17 @@ __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uns
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+// a right-hand-side value stored as TB (T itself, or a scaled FP16 copy of
+// an FP32 residual) widened to T exactly
+template <typename T, typename TB>
+__device__ __forceinline__ T buf_load_rhs(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    if constexpr (sizeof(TB) == 2) {
+        return (T)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+    } else {
+        return buf_load<T>(r, off);
+    }
+}
 __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off)
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
@@ -204,10 +215,10 @@ __device__ __forceinline__ void unrolled(int t0, F& f, std::integer_sequence<int
 template <typename T>
 constexpr int kMinWavesPerSimd = sizeof(T) == 4 ? 4 : 1;
 
-template <typename T, int NT, int WAVES>
+template <typename T, typename TB, int NT, int WAVES>
 __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused(int nx, int ny, int nz, int zchunk,
                                                             int tx, int ty, int ntiles,
-                                                            const T* __restrict__ b, const T* __restrict__ p,
+                                                            const TB* __restrict__ b, const T* __restrict__ p,
                                                             T* __restrict__ out, StageCoefs<T> kc)
 {
     // Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD
@@ -234,6 +245,9 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
     const int z0 = bz * zchunk, z1 = min(nz, z0 + zchunk);
     const long long plane = (long long)nx * ny;
     const unsigned pbytes = (unsigned)(plane * (long long)sizeof(T));
+    const unsigned bbytes = (unsigned)(plane * (long long)sizeof(TB));
+    // b offsets: this thread's p offsets scaled to TB's size
+    constexpr int kBShift = sizeof(T) / sizeof(TB) == 2 ? 1 : 0;
 
     // global offsets of this thread's columns (periodic wrap)
     const int gx = ((x0 + lane) % nx + nx) % nx;
@@ -288,11 +302,11 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
     const int t_end = z1 - 1 + NT;  // the final stage reaches plane z1 - 1
     {
         const long long o = plane * t_begin;
-        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(p + o, pbytes), rb = plane_rsrc(b + o, pbytes);
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(p + o, pbytes), rb = plane_rsrc(b + o, bbytes);
 #pragma unroll
         for (int m = 0; m < PTS; ++m) {
             Pn[m] = buf_load<T>(rp, col[m]);
-            Bz[0][m] = buf_load<T>(rb, col[m]);
+            Bz[0][m] = buf_load_rhs<T, TB>(rb, col[m] >> kBShift);
         }
     }
     // halo row of the first stage: plane t + 1 is requested (Ph) when plane
@@ -313,7 +327,7 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
         // first: loads complete in order)
         {
             const long long o = plane * min(t + 1, nz - 1);
-            const __amdgpu_buffer_rsrc_t rp = plane_rsrc(p + o, pbytes), rb = plane_rsrc(b + o, pbytes);
+            const __amdgpu_buffer_rsrc_t rp = plane_rsrc(p + o, pbytes), rb = plane_rsrc(b + o, bbytes);
             if (hrow >= 0) {
                 Vh = Ph;
                 Ph = buf_load<T>(rp, hcol);
@@ -322,7 +336,7 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
             for (int m = 0; m < PTS; ++m) {
                 V[0][vs(0)][m] = Pn[m];
                 Pn[m] = buf_load<T>(rp, col[m]);
-                Bz[bs(-1)][m] = buf_load<T>(rb, col[m]);
+                Bz[bs(-1)][m] = buf_load_rhs<T, TB>(rb, col[m] >> kBShift);
             }
         }
         // stages 1..NT: stage s produces plane q = t - s from stage s-1's
@@ -373,8 +387,8 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
     for (int tb = t_begin; tb <= t_end; tb += kUnroll) unrolled(tb, step, std::make_integer_sequence<int, kUnroll>{});
 }
 
-// Workgroups of k_relax_fused<T, NT, WAVES> resident on the device at once.
-template <typename T, int NT, int WAVES>
+// Workgroups of k_relax_fused<T, TB, NT, WAVES> resident on the device at once.
+template <typename T, typename TB, int NT, int WAVES>
 int resident_workgroups()
 {
     static int cached = 0;  // per kernel instance; one device model per process
@@ -382,7 +396,7 @@ int resident_workgroups()
         int dev = 0, cus = 0, per_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_relax_fused<T, NT, WAVES>, 64 * WAVES, 0) !=
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_relax_fused<T, TB, NT, WAVES>, 64 * WAVES, 0) !=
                 hipSuccess)
             return 0;
         cached = std::max(1, cus * per_cu);
@@ -390,13 +404,13 @@ int resident_workgroups()
     return cached;
 }
 
-template <typename T, int NT, int WAVES>
-hipError_t launch_fused(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, hipStream_t s)
+template <typename T, typename TB, int NT, int WAVES>
+hipError_t launch_fused(const Geo& g, const TB* b, const T* p, T* out, const Weights& wts, hipStream_t s)
 {
     constexpr int OX = kTileX - 2 * NT, OY = kRows - 2 * NT;
     const int tx = (g.nx + OX - 1) / OX, ty = (g.ny + OY - 1) / OY;
     const long long tiles = (long long)tx * ty;
-    const int resident = resident_workgroups<T, NT, WAVES>();
+    const int resident = resident_workgroups<T, TB, NT, WAVES>();
     if (resident == 0) return hipErrorInvalidDevice;
     // z-chunks: the fewest rounds of resident workgroups times steps per
     // chunk (a chunk of zc planes takes zc + 2 NT steps)
@@ -414,15 +428,15 @@ hipError_t launch_fused(const Geo& g, const T* b, const T* p, T* out, const Weig
     nzc = (g.nz + zchunk - 1) / zchunk;
     const int ntiles = (int)(tiles * nzc);
     const int grid = (ntiles + kXcds - 1) / kXcds * kXcds;  // whole rounds over the XCDs
-    hipLaunchKernelGGL((k_relax_fused<T, NT, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, g.nx, g.ny, g.nz, zchunk,
+    hipLaunchKernelGGL((k_relax_fused<T, TB, NT, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, g.nx, g.ny, g.nz, zchunk,
                        tx, ty, ntiles, b, p, out, stage_coefs<T>(g, wts, NT));
     return hipGetLastError();
 }
 
 // One sweep per launch, one thread per (i, j) column marching along z with the
 // vertical neighbours in registers; used for grids narrower than a tile.
-template <typename T>
-__global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchunk, const T* __restrict__ b,
+template <typename T, typename TB>
+__global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchunk, const TB* __restrict__ b,
                                                const T* __restrict__ p, T* __restrict__ out, StageCoefs<T> kc)
 {
     const Coef<T> c = coef_of<T>(kc, 0);
@@ -440,7 +454,7 @@ __global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchun
     for (int k = k0; k < k1; ++k, o += plane) {
         const T pt = k + 1 < nz ? p[o + plane + row + i] : pc;
         out[o + row + i] = sweep_point<T>(c, plane_coef(c, k, nz), p[o + row + im], p[o + row + ip], p[o + rowm + i],
-                                          p[o + rowp + i], pt, pb, pc, b[o + row + i]);
+                                          p[o + rowp + i], pt, pb, pc, (T)b[o + row + i]);
         pb = pc;
         pc = pt;
     }
@@ -453,27 +467,39 @@ bool relax_fusable(const Geo& g)
     return g.nx >= kTileX && g.ny >= kTileY && (long long)g.nx * g.ny < (1LL << 29);
 }
 
-template <typename T>
-hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, int nfused, hipStream_t s)
+template <typename T, typename TB>
+hipError_t relax_impl(const Geo& g, const TB* b, const T* p, T* out, const Weights& wts, int nfused, hipStream_t s)
 {
     if (nfused == 1 || !relax_fusable(g)) {
         if (nfused != 1) return hipErrorInvalidValue;
         const March m = march_shape(g, 2048);
-        hipLaunchKernelGGL(k_relax<T>, m.grid, m.block, 0, s, g.nx, g.ny, g.nz, m.kchunk, b, p, out,
+        hipLaunchKernelGGL((k_relax<T, TB>), m.grid, m.block, 0, s, g.nx, g.ny, g.nz, m.kchunk, b, p, out,
                            stage_coefs<T>(g, wts, 1));
         return hipGetLastError();
     }
     switch (nfused) {
-    case 2: return launch_fused<T, 2, kWaves<T>>(g, b, p, out, wts, s);
-    case 3: return launch_fused<T, 3, kWaves<T>>(g, b, p, out, wts, s);
-    case 4: return launch_fused<T, 4, kWaves<T>>(g, b, p, out, wts, s);
+    case 2: return launch_fused<T, TB, 2, kWaves<T>>(g, b, p, out, wts, s);
+    case 3: return launch_fused<T, TB, 3, kWaves<T>>(g, b, p, out, wts, s);
+    case 4: return launch_fused<T, TB, 4, kWaves<T>>(g, b, p, out, wts, s);
     }
     if constexpr (sizeof(T) == 4) {  // FP64 rings do not fit deeper pipelines in registers
-        if (nfused == 5) return launch_fused<T, 5, kWaves<T>>(g, b, p, out, wts, s);
+        if (nfused == 5) return launch_fused<T, TB, 5, kWaves<T>>(g, b, p, out, wts, s);
     }
     return hipErrorInvalidValue;
 }
+
+template <typename T>
+hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, int nfused, hipStream_t s)
+{
+    return relax_impl<T, T>(g, b, p, out, wts, nfused, s);
+}
 template hipError_t relax<double>(const Geo&, const double*, const double*, double*, const Weights&, int, hipStream_t);
 template hipError_t relax<float>(const Geo&, const float*, const float*, float*, const Weights&, int, hipStream_t);
+
+hipError_t relax(const Geo& g, const _Float16* b, const float* p, float* out, const Weights& wts, int nfused,
+                 hipStream_t s)
+{
+    return relax_impl<float, _Float16>(g, b, p, out, wts, nfused, s);
+}
 
 }  // namespace stp

@@ -59,6 +59,9 @@ def test_workspace_bytes_valid_and_invalid():
     # the extrapolated warm start keeps p^{n-1} (order 1) and p^{n-2} (order 2)
     for order in (1, 2):
         assert lib.stp_workspace_bytes(ctypes.byref(cfg(extrap_order=order))) == n_ok + order * 8 * n
+    # the FP16 right-hand side of the mixed passes: nx*ny*nz halves
+    mixed = lib.stp_workspace_bytes(ctypes.byref(cfg(precision=1)))
+    assert lib.stp_workspace_bytes(ctypes.byref(cfg(precision=1, mixed_rhs16=1))) == mixed + 2 * n
     # the least-squares guess keeps proj_depth solutions and their right-hand sides
     for depth in (1, 8):
         assert lib.stp_workspace_bytes(ctypes.byref(cfg(proj_depth=depth))) == n_ok + 2 * depth * 8 * n
@@ -66,7 +69,8 @@ def test_workspace_bytes_valid_and_invalid():
                 dict(precision=7), dict(poisson_maxit=0), dict(poisson_rtol=-1.0), dict(srj_reduction=1.5),
                 dict(les=2), dict(tblock=-1), dict(tblock=6), dict(cn_tol=2.0), dict(srj_m=4),
                 dict(extrap_order=3), dict(extrap_order=1, warm_start=1), dict(proj_depth=-1),
-                dict(proj_depth=9), dict(proj_depth=2, warm_start=1)):
+                dict(proj_depth=9), dict(proj_depth=2, warm_start=1), dict(mixed_rhs16=1),
+                dict(precision=1, mixed_rhs16=2)):
         assert lib.stp_workspace_bytes(ctypes.byref(cfg(**bad))) == 0, bad
     assert lib.stp_workspace_bytes(None) == 0
 

@@ -158,22 +158,24 @@ def test_residual_norm(gpu, g):
     assert got == pytest.approx(math.sqrt(s2), rel=1e-12)
 
 
+@pytest.mark.parametrize("rhs16", [0, 1])
 @pytest.mark.parametrize("g", GRIDS[:2] + [GRIDS[4]])
-def test_mixed_solve_against_fp64_oracle(gpu, g):
+def test_mixed_solve_against_fp64_oracle(gpu, g, rhs16):
     """FP32 sweeps inside the FP64 defect correction reach the FP64 residual
-    test; the solution matches the FP64 oracle within 1e-5."""
+    test (also with each pass's right-hand side stored in FP16); the solution
+    matches the FP64 oracle within 1e-5."""
     import torch
     from paper_1511_07800_amd import STP_MIXED
     P = oracle.make_params(*g)
     om = osched.srj_schedule(*g)
     b = inputs.poisson_rhs(g[0], g[1], g[2], seed=17)
     p_ref, st, *_ = oracle.poisson_srj(P, b, np.zeros_like(b), om, 1e-12, 100)
-    ch = channel(g, precision=STP_MIXED)
+    ch = channel(g, precision=STP_MIXED, mixed_rhs16=rhs16)
     pd = to_dev(torch, np.zeros_like(b))
     stats, rc = ch.poisson_solve(to_dev(torch, b), pd, 1e-10, 50)
     assert rc == 0 and stats["relres"] <= 1e-10
     err = rel_l2(pd.cpu().numpy(), p_ref)
-    print(f"mixed solve grid={g} outer={stats['outer']} rel_l2={err:.3e}")
+    print(f"mixed solve grid={g} rhs16={rhs16} outer={stats['outer']} rel_l2={err:.3e}")
     assert err <= 1e-5
 
 
@@ -181,7 +183,7 @@ FULL = {512: (512, 256, 192, 4 * math.pi, 2 * math.pi, 2.0), 1024: (1024, 512, 3
 
 
 @pytest.mark.parametrize("size", [512, 1024])
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16rhs"])
 def test_full_size_sweep_sampled(gpu, dtype, size):
     """One sweep at the 512x256x192 LES grid and at the largest one
     (1024x512x384, 2e8 cells), checked on about 4000 sampled cells (walls,
@@ -193,15 +195,16 @@ def test_full_size_sweep_sampled(gpu, dtype, size):
     P = oracle.make_params(*g)
     r = inputs.rng(18)
     tdt = torch.float64 if dtype == "f64" else torch.float32
+    bdt = torch.float16 if dtype == "f16rhs" else tdt
     p = r.standard_normal((nz, ny, nx))
     b = r.standard_normal((nz, ny, nx))
-    if dtype == "f32":
+    if dtype != "f64":
         p = p.astype(np.float32).astype(np.float64)
-        b = b.astype(np.float32).astype(np.float64)
+        b = b.astype(np.float16 if dtype == "f16rhs" else np.float32).astype(np.float64)
     omega = 37.5
     ch = channel(g)
     pd = to_dev(torch, p, tdt)
-    ch.relax(to_dev(torch, b, tdt), pd, [omega])
+    ch.relax(to_dev(torch, b, bdt), pd, [omega])
     got = pd.cpu().double().numpy().ravel()
     n = nx * ny * nz
     plane = nx * ny
@@ -213,7 +216,7 @@ def test_full_size_sweep_sampled(gpu, dtype, size):
 
 
 @pytest.mark.parametrize("g", [(70, 45, 33, 2.0, 1.5, 1.0), (130, 64, 40, 4.0, 2.0, 2.0), (64, 32, 5, 1.0, 1.0, 1.0)])
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16rhs"])
 @pytest.mark.parametrize("nt", [2, 3, 4, 5])
 def test_fused_sweeps_equal_single_sweeps_bitwise(gpu, g, dtype, nt):
     """NT sweeps fused into one launch (LDS tile, z-march) reproduce NT single
@@ -225,7 +228,7 @@ def test_fused_sweeps_equal_single_sweeps_bitwise(gpu, g, dtype, nt):
     tdt = torch.float64 if dtype == "f64" else torch.float32
     r = inputs.rng(19)
     p = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
-    b = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
+    b = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), torch.float16 if dtype == "f16rhs" else tdt)
     om = [1.3, 57.0, 0.6, 3.1, 11.0, 0.9, 2.2, 40.0, 0.7, 5.5, 1.9, 23.0, 1.1][: 2 * nt + 1]
     ch1 = channel(g, tblock=1)
     chf = channel(g, tblock=nt)
@@ -237,7 +240,8 @@ def test_fused_sweeps_equal_single_sweeps_bitwise(gpu, g, dtype, nt):
     assert torch.equal(p1, pf)
 
 
-@pytest.mark.parametrize("dtype,nt,size", [("f32", 4, 512), ("f32", 5, 512), ("f64", 4, 512), ("f32", 4, 1024)])
+@pytest.mark.parametrize("dtype,nt,size", [("f32", 4, 512), ("f32", 5, 512), ("f64", 4, 512), ("f32", 4, 1024),
+                                           ("f16rhs", 4, 512)])
 def test_fused_sweeps_full_size_bitwise(gpu, dtype, nt, size):
     """The fused launch at the benchmark grid (512x256x192, the launch
     configuration the bench times: several z-chunks per tile column, ragged
@@ -250,7 +254,7 @@ def test_fused_sweeps_full_size_bitwise(gpu, dtype, nt, size):
     tdt = torch.float64 if dtype == "f64" else torch.float32
     r = inputs.rng(23)
     p = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
-    b = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), tdt)
+    b = to_dev(torch, r.standard_normal((g[2], g[1], g[0])), torch.float16 if dtype == "f16rhs" else tdt)
     om = [1.3, 57.0, 0.6, 3.1, 11.0, 0.9, 2.2, 40.0, 0.7, 5.5, 1.9, 23.0][: 2 * nt]
     p1, pf = p.clone(), p.clone()
     channel(g, tblock=1).relax(b, p1, om)
