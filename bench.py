@@ -142,7 +142,8 @@ def measured_traffic(nx, ny, nz, tblock):
 def profile_kernels(wl):
     """Kernels for counter collection: a torch copy of 64 Mi floats (512 MiB
     moved: 256 MiB read, 256 MiB written), then 8 launches each of the fused
-    FP32 relaxation kernel and the single-sweep FP32 kernel."""
+    FP32 relaxation kernel, the single-sweep FP32 kernel and the fused kernel
+    with an FP16 right-hand side."""
     import torch
     from paper_1511_07800_amd import Channel, inputs
     a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -158,6 +159,10 @@ def profile_kernels(wl):
         om = ch.schedule()
         ch.relax(b, p, [om[k % len(om)] for k in range(8 * tb)])
         torch.cuda.synchronize()
+        if tb == 4:
+            p.zero_()
+            ch.relax(b.half(), p, [om[k % len(om)] for k in range(8 * tb)])
+            torch.cuda.synchronize()
         ch.close()
     print("profile-kernels done", file=sys.stderr, flush=True)
 
