@@ -50,8 +50,8 @@ def parse():
     ap.add_argument("--fixed-cycles", action="store_true", help="repeat the fixed 1e-3 SRJ cycle (no adaptive sizing)")
     ap.add_argument("--sweeps", type=int, default=200, help="sweeps in the kernel roofline timing")
     ap.add_argument("--profile-fastest", action="store_true",
-                    help="run only the fastest variant (least-squares guess refined by the network), for a "
-                         "kernel trace of its steps")
+                    help="run only the fastest variant (least-squares guess refined by the network, each "
+                         "pass's right-hand side in FP16), for a kernel trace of its steps")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run a plain copy of known size and the relaxation kernels (for rocprofv3 counters)")
     return ap.parse_args()
@@ -271,11 +271,11 @@ def main():
         return
     if args.profile_fastest:
         from paper_1511_07800_amd import STP_WS_LEARNED, warmstart
-        ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED, proj_depth=PROJ_DEPTH)
+        ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED, proj_depth=PROJ_DEPTH, rhs16=1)
         ch.net_init(training=False)
         warmstart.load_weights(ch, os.path.join(ROOT, "paper_1511_07800_amd", "weights", args.weights))
-        t, acc, _ = time_steps(ch, args.steps, args.warmup, "learned+lsq+mixed")
-        print(json.dumps({"variant": "learned+lsq+mixed", "warmup": args.warmup, "steps": args.steps,
+        t, acc, _ = time_steps(ch, args.steps, args.warmup, "learned+lsq+mixed(rhs16)")
+        print(json.dumps({"variant": "learned+lsq+mixed(rhs16)", "warmup": args.warmup, "steps": args.steps,
                           "ms_per_step": round(1e3 * t / args.steps, 2),
                           "sweeps_per_step": acc["sweeps"] / args.steps}), flush=True)
         return
