@@ -415,8 +415,10 @@ stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, in
         const long long count = (long long)cyc.size() * inner;
         sweeps += count;
         stp_status r2;
-        if (rhs16 && rn > 0.0 && std::isfinite(rn)) {
-            const double scale = std::sqrt((double)ctx->g.n) / rn;
+        // unit-rms scaling: every element is at most sqrt(n) (< FP16's 65504 for
+        // n < 4e9); a residual too small for an FP32 scale takes the FP32 path
+        const double scale = rn > 0.0 ? std::sqrt((double)ctx->g.n) / rn : 0.0;
+        if (rhs16 && std::isfinite(rn) && scale > 0.0 && std::isfinite((float)scale)) {
             CHK(half_scaled(ctx->r16, ctx->r32, ctx->g.n, (float)scale, ctx->s));
             r2 = timed_sweeps<float, _Float16>(ctx, ctx->r16, &cur, &oth, cyc, count, st);
             if (r2 != STP_OK) return r2;
