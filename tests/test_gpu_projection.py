@@ -22,12 +22,12 @@ pytestmark = pytest.mark.gpu
 G = dict(nx=128, ny=64, nz=64, lx=4 * math.pi, ly=2 * math.pi, lz=2.0, nu=1.0 / 180, dpdx=-1.0, dt=4e-5)
 
 
-def channel(proj_depth=0, extrap_order=0, precision=1, rtol=1e-8, g=G, maxit=200):
+def channel(proj_depth=0, extrap_order=0, precision=1, rtol=1e-8, g=G, maxit=200, rhs16=0):
     import torch
     from paper_1511_07800_amd import Channel
     ch = Channel(g["nx"], g["ny"], g["nz"], g["lx"], g["ly"], g["lz"], nu=g["nu"], dpdx=g["dpdx"], dt=g["dt"],
                  les=1, precision=precision, poisson_rtol=rtol, poisson_maxit=maxit, srj_adaptive=1,
-                 srj_reduction=1e-4, extrap_order=extrap_order, proj_depth=proj_depth)
+                 srj_reduction=1e-4, extrap_order=extrap_order, proj_depth=proj_depth, mixed_rhs16=rhs16)
     u, v, w = inputs.channel_state(g["nx"], g["ny"], g["nz"], g["lz"], g["nu"], g["dpdx"], noise=0.1, seed=7901)
     for k, a in enumerate((u, v, w)):
         ch.field(k).copy_(torch.from_numpy(a))
@@ -205,3 +205,26 @@ def test_learned_refinement_of_least_squares_guess_reports_p_n(gpu):
         assert st["poisson"]["relres0"] == pytest.approx(min(cands), rel=1e-9)
         assert st["poisson"]["relres"] <= 1e-8
     ch.close()
+
+
+def test_fp16_right_hand_side_les_steps(gpu):
+    """LES steps with each mixed pass's right-hand side stored in FP16
+    (mixed_rhs16), from p^n and from the least-squares guess: every solve
+    meets the tolerance and the fields agree with the FP32-right-hand-side run
+    to the mixed-precision bound."""
+    import torch
+    from paper_1511_07800_amd import STP_U, STP_V, STP_W, STP_P
+    for depth in (0, 8):
+        print(f"FP16 right-hand side, proj_depth {depth}", flush=True)
+        out = {}
+        for rhs16 in (0, 1):
+            ch = channel(proj_depth=depth, rhs16=rhs16)
+            for _ in range(12):
+                st = ch.step(1)
+                assert st["poisson"]["relres"] <= 1e-8
+            out[rhs16] = [ch.field(k).clone() for k in (STP_U, STP_V, STP_W, STP_P)]
+            ch.close()
+        for name, a, r in zip("uvwp", out[1], out[0]):
+            err = float((a - r).norm() / r.norm())
+            print(name, f"{err:.2e}", flush=True)
+            assert err <= 1e-5
