@@ -276,3 +276,52 @@ def test_adaptive_cycles_reach_tolerance_and_match_direct_solve():
     om = srj_schedule.srj_schedule(*g)
     _, _, cyc_f, _, _ = oracle.poisson_srj(P, b, np.zeros_like(b), om, 1e-10, 100)
     assert cyc_f * len(om) > sweeps
+
+
+def _leja_violation(order, nodes, band=(0.5e-9, 2e-9)):
+    """First step at which `order` (a sequence of node values) breaks the Leja
+    rule of Sec. 3.4's reading: the first node has the largest magnitude;
+    each later node maximises the sum of log distances to the nodes already
+    placed (math.fsum, an independent summation), and among candidates tied
+    within a relative 1e-9 the one of lowest index in `nodes` wins.  Returns
+    None when the rule holds.  Candidates inside the tolerance band around
+    the tie threshold are not judged (round-off may decide them)."""
+    nodes = [float(x) for x in nodes]
+    idx = {}
+    for i, x in enumerate(nodes):
+        idx.setdefault(x, i)
+    seq = [idx[float(x)] for x in order]
+    if sorted(seq) != list(range(len(nodes))):
+        return "not a permutation"
+    big = max(abs(x) for x in nodes)
+    first = min(i for i, x in enumerate(nodes) if abs(x) == big)
+    if seq[0] != first:
+        return 0
+    placed = [seq[0]]
+    for t in range(1, len(seq)):
+        rest = [i for i in range(len(nodes)) if i not in placed]
+        score = {i: math.fsum(math.log(abs(nodes[i] - nodes[j])) for j in placed) for i in rest}
+        top = max(score.values())
+        scale = max(1.0, abs(top))
+        c = seq[t]
+        if score[c] < top - band[1] * scale:
+            return t
+        for i in rest:
+            if i < c and score[i] >= top - band[0] * scale:
+                return t
+        placed.append(c)
+    return None
+
+
+@pytest.mark.parametrize("m", [7, 16, 33, 64])
+def test_leja_order_property(m):
+    """leja_order follows the Leja rule step by step (brute force over the
+    remaining nodes), and a planted swap of two later nodes breaks it."""
+    a, b = srj_schedule.kappa_bounds(64, 32, 32, 4 * math.pi, 2 * math.pi, 2.0)
+    x = srj_schedule.chebyshev_nodes(a, b, m)
+    order = srj_schedule.leja_order(x)
+    assert _leja_violation(order, x) is None
+    for t in (1, m // 2, m - 2):
+        bad = order.copy()
+        bad[t], bad[t + 1] = bad[t + 1], bad[t]
+        assert _leja_violation(bad, x) is not None, t

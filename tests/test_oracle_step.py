@@ -288,3 +288,61 @@ def test_eddy_viscosity_strain_second_order():
         s_num = (nut - 1.0) / ((delta * phi) ** 2)[:, None, None]
         errs.append(np.abs(s_num**2 - sample(s2, xc, yc, zc))[2:-2].max())
     assert 1.85 <= math.log2(errs[0] / errs[1]) <= 2.2, errs
+
+
+# ------------------------------------------------------------ diagnostics --
+
+
+@pytest.mark.parametrize("nz", [16, 15])
+def test_diagnostics_closed_forms(nz):
+    """or_diagnostics on fields with closed-form answers (the CFL rule of
+    Sec. 3.2, the centreline velocity of Sec. 6):
+    * the discrete steady profile u_k = |G| z_k (lz - z_k)/(2 nu) + |G| dz^2/(8 nu)
+      has mean |G| lz^2/(12 nu) + |G| dz^2/(6 nu) over the midpoints z_k, its
+      largest value |G| lz^2/(8 nu) (+ |G| dz^2/(8 nu) when nz is odd, where a
+      cell centre sits on the centreline), and that same value on the
+      centreline;
+    * v = c_v everywhere and w = c_w on the interior z-faces give
+      CFL = max(U_max/dx, |c_v|/dy, |c_w|/dz) dt, and a divergence of
+      c_w/dz in the first and -c_w/dz in the last cell layer, 0 elsewhere."""
+    nx, ny, lx, ly, lz = 12, 6, 3.0, 2.0, 2.0
+    nu, g, dt = 0.01, 0.02, 1e-3
+    P = oracle.make_params(nx, ny, nz, lx, ly, lz, nu=nu, dpdx=-g, dt=dt)
+    h = lz / nz
+    u = np.repeat(np.repeat(inputs.laminar_profile(nz, lz, nu, -g)[:, None, None], ny, 1), nx, 2)
+    umax = g * lz**2 / (8 * nu) + (g * h * h / (8 * nu) if nz % 2 else 0.0)
+    ubulk = g * lz**2 / (12 * nu) + g * h * h / (6 * nu)
+    for cv, cw in ((0.0, 0.0), (3.0 * ly / ny / (lx / nx), 0.0), (0.0, -4.0 * h / (lx / nx)), (0.5, 0.25)):
+        v = np.full((nz, ny, nx), cv)
+        w = np.zeros((nz + 1, ny, nx))
+        w[1:nz] = cw
+        st = oracle.diagnostics(P, u, v, w)
+        assert st["u_max"] == pytest.approx(umax, rel=1e-14)
+        assert st["u_centre"] == pytest.approx(umax, rel=1e-14)
+        assert st["u_bulk"] == pytest.approx(ubulk, rel=1e-14)
+        cfl = max(umax * dt / (lx / nx), abs(cv) * dt / (ly / ny), abs(cw) * dt / h)
+        assert st["cfl"] == pytest.approx(cfl, rel=1e-14)
+        assert st["max_div"] == pytest.approx(abs(cw) / h, rel=1e-14, abs=0.0)
+
+
+def test_eddy_viscosity_field_and_max_closed_form():
+    """u = S z, v = w = 0: the odd ghost below the bottom wall continues the
+    line, so |S| = S in every cell but the top one; there the ghost above
+    the wall gives the x-z strains S/2 (lower edges) and -(u_top)/dz (upper
+    edges, u_top = S (lz - dz/2)), so |S|^2 = 4 mean(S13^2) =
+    (S^2 + (2 u_top/dz)^2)/2.  nu_T = nu + (C_S Delta phi_w)^2 |S| everywhere
+    (Sec. 2.2), and or_nut returns its maximum."""
+    nx, ny, nz, lx, ly, lz = 6, 4, 12, 1.5, 1.0, 2.0
+    P = oracle.make_params(nx, ny, nz, lx, ly, lz, nu=1 / 180, dpdx=-1.0, dt=1e-4, les=1)
+    S, h = 2.5, lz / nz
+    zc = (np.arange(nz) + 0.5) * h
+    u = np.repeat(np.repeat((S * zc)[:, None, None], ny, 1), nx, 2)
+    nut, mx = oracle.nut(P, u, np.zeros_like(u), np.zeros((nz + 1, ny, nx)))
+    smag = np.full(nz, S)
+    utop = S * (lz - h / 2)
+    smag[-1] = math.sqrt(0.5 * (S * S + (2 * utop / h) ** 2))
+    delta = 2 * (lx / nx * ly / ny * h) ** (1 / 3)
+    phi = 1 - np.exp(-np.minimum(zc, lz - zc) * math.sqrt(lz / 2) / P.nu / 25.0)
+    ref = P.nu + (0.1 * delta * phi) ** 2 * smag
+    np.testing.assert_allclose(nut, np.broadcast_to(ref[:, None, None], nut.shape), rtol=1e-13)
+    assert mx == pytest.approx(ref.max(), rel=1e-13)
