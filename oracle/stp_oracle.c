@@ -45,9 +45,11 @@
  *   - Poisson stop test ||b - L p||_2 <= rtol ||b||_2, checked before the
  *     first cycle and after every full cycle; rtol = 0 runs maxit cycles.
  *
- * Arithmetic: FP64 throughout, built with -O2 -ffp-contract=off.  The plane
- * loops of the Laplacian and the sweep may run on OpenMP threads; every
- * value is computed exactly as in a serial run and every reduction is serial.
+ * Arithmetic: FP64 throughout, built with -O2 -ffp-contract=off.  The loops
+ * over z-planes of the stencils (Laplacian, sweep, divergence, correction,
+ * eddy viscosity, viscous and explicit terms) may run on OpenMP threads:
+ * every value is computed by the same expression as in a serial run, and
+ * every reduction (sums, maxima, norms) is a serial loop.
  */
 #include <math.h>
 #include <stdint.h>
@@ -217,6 +219,23 @@ static double mean(const double* a, size_t n)
     return s / (double)n;
 }
 
+/* The m sweeps of one cycle, in order, alternating between p and the
+ * scratch q (each sweep reads one array and writes the other); the cycle's
+ * result is left in p. */
+static void srj_cycle(const or_params* P, const double* omega, int m, double* p, const double* b, double* q,
+                      double* lap)
+{
+    double* cur = p;
+    double* nxt = q;
+    for (int s = 0; s < m; ++s) {
+        srj_sweep_into(P, omega[s], cur, b, nxt, lap);
+        double* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (cur != p) memcpy(p, cur, or_ncell(P) * sizeof(double));
+}
+
 /* Scheduled Relaxation Jacobi (Sec. 3.4): the M-sweep cycle omega[0..m-1]
  * is applied repeatedly; convergence is tested before the first cycle and
  * after each full cycle.  p holds the initial guess on entry and the
@@ -235,11 +254,7 @@ int or_poisson_srj(const or_params* P, const double* b, double* p, const double*
     double rn = sqrt(or_residual(P, p, b, r));
     *relres0 = rn / floor_b;
     /* one cycle: the m sweeps of the schedule, in order */
-#define SRJ_CYCLE()                                              \
-    for (int s = 0; s < m; ++s) {                                \
-        srj_sweep_into(P, omega[s], p, b, q, lap);               \
-        memcpy(p, q, n * sizeof(double));                        \
-    }
+#define SRJ_CYCLE() srj_cycle(P, omega, m, p, b, q, lap)
     if (rtol > 0.0) {
         while (!(rn <= rtol * floor_b)) {
             if (!isfinite(rn)) { status = -5; break; }
@@ -270,6 +285,7 @@ int or_poisson_srj(const or_params* P, const double* b, double* p, const double*
 void or_divergence(const or_params* P, const double* u, const double* v, const double* w, double* out)
 {
     const double dx = hx(P), dy = hy(P), dz = hz(P);
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < P->nz; ++k)
         for (int j = 0; j < P->ny; ++j)
             for (int i = 0; i < P->nx; ++i)
@@ -283,12 +299,14 @@ void or_divergence(const or_params* P, const double* u, const double* v, const d
 void or_project(const or_params* P, const double* p, double* u, double* v, double* w)
 {
     const double dx = hx(P), dy = hy(P), dz = hz(P), dt = P->dt;
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < P->nz; ++k)
         for (int j = 0; j < P->ny; ++j)
             for (int i = 0; i < P->nx; ++i) {
                 u[ix(P, i, j, k)] -= dt * (p[ix(P, i, j, k)] - p[ix(P, i - 1, j, k)]) / dx;
                 v[ix(P, i, j, k)] -= dt * (p[ix(P, i, j, k)] - p[ix(P, i, j - 1, k)]) / dy;
             }
+#pragma omp parallel for schedule(static)
     for (int k = 1; k < P->nz; ++k)
         for (int j = 0; j < P->ny; ++j)
             for (int i = 0; i < P->nx; ++i)
@@ -320,6 +338,7 @@ double or_nut(const or_params* P, const double* u, const double* v, const double
         return P->nu;
     }
     const double delta = 2.0 * cbrt(dx * dy * dz);
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < P->nz; ++k)
         for (int j = 0; j < P->ny; ++j)
             for (int i = 0; i < P->nx; ++i) {
@@ -350,8 +369,9 @@ double or_nut(const or_params* P, const double* u, const double* v, const double
                 const double l = P->cs * delta * van_driest(P, zc);
                 const double val = P->nu + l * l * smag;
                 nut[ix(P, i, j, k)] = val;
-                if (val > mx) mx = val;
             }
+    for (size_t c = 0; c < n; ++c)
+        if (nut[c] > mx) mx = nut[c];
     return mx;
 }
 
@@ -381,6 +401,7 @@ void or_visc_diff(const or_params* P, int c, const double* nut, const double* f,
     const double dx = hx(P), dy = hy(P), dz = hz(P);
     const int nz = P->nz;
     if (c == 0) {
+#pragma omp parallel for schedule(static)
         for (int k = 0; k < nz; ++k)
             for (int j = 0; j < P->ny; ++j)
                 for (int i = 0; i < P->nx; ++i) {
@@ -394,6 +415,7 @@ void or_visc_diff(const or_params* P, int c, const double* nut, const double* f,
                     out[ix(P, i, j, k)] = tx / (dx * dx) + ty / (dy * dy) + tz / (dz * dz);
                 }
     } else if (c == 1) {
+#pragma omp parallel for schedule(static)
         for (int k = 0; k < nz; ++k)
             for (int j = 0; j < P->ny; ++j)
                 for (int i = 0; i < P->nx; ++i) {
@@ -412,6 +434,7 @@ void or_visc_diff(const or_params* P, int c, const double* nut, const double* f,
                 out[ix(P, i, j, 0)] = 0.0;
                 out[ix(P, i, j, nz)] = 0.0;
             }
+#pragma omp parallel for schedule(static)
         for (int k = 1; k < nz; ++k)
             for (int j = 0; j < P->ny; ++j)
                 for (int i = 0; i < P->nx; ++i) {
@@ -436,6 +459,7 @@ void or_explicit(const or_params* P, const double* u, const double* v, const dou
 {
     const double dx = hx(P), dy = hy(P), dz = hz(P);
     const int nz = P->nz;
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < P->ny; ++j)
             for (int i = 0; i < P->nx; ++i) {
@@ -488,6 +512,7 @@ void or_explicit(const or_params* P, const double* u, const double* v, const dou
             ew[ix(P, i, j, 0)] = 0.0;
             ew[ix(P, i, j, nz)] = 0.0;
         }
+#pragma omp parallel for schedule(static)
     for (int k = 1; k < nz; ++k)
         for (int j = 0; j < P->ny; ++j)
             for (int i = 0; i < P->nx; ++i) {
