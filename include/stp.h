@@ -73,7 +73,9 @@ typedef enum {
 
 typedef enum {
     STP_FP64 = 0,  /* every sweep and reduction in FP64 (the paper's method) */
-    STP_MIXED = 1  /* FP32 relaxation sweeps inside an FP64 defect correction */
+    STP_MIXED = 1  /* FP32 relaxation sweeps inside an FP64 defect correction; each FP32 pass
+                      solves for a power-of-two multiple of the residual that lies in FP32's
+                      normal range, so tiny and huge right-hand sides keep FP32 precision */
 } stp_precision;
 
 typedef enum {
@@ -132,7 +134,8 @@ typedef struct {
                                   Adds 2 proj_depth arrays of nx*ny*nz doubles to the workspace.  Needs
                                   STP_WS_PREV or STP_WS_LEARNED.  The stop test is unchanged. */
     int32_t mixed_rhs16;       /* STP_MIXED only: 1 stores each FP32 pass's right-hand side (the FP64
-                                  residual) as FP16 after scaling it to unit rms, so the sweeps read 2
+                                  residual) as FP16 after scaling it to about unit rms by a power of
+                                  two (the correction is scaled back exactly), so the sweeps read 2
                                   instead of 4 bytes of it per cell; the sweeps still compute in FP32
                                   and the FP64 residual test is unchanged, but one pass then reduces
                                   the residual by at most about 1e-3 (FP16 rounds each element to

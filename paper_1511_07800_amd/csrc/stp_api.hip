@@ -403,10 +403,22 @@ stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, in
     st->status = STP_OK;
     int outer = 0;
     long long sweeps = 0;
-    // with mixed_rhs16 the pass's right-hand side is an FP16 copy of the
-    // residual scaled to unit rms, which bounds what one pass can reduce
+    // The FP32 pass solves L e = s r for a power of two s (r32 holds s r, which
+    // rounds exactly like r) and the correction is e / s: the scale keeps the
+    // copy of a tiny or huge residual inside FP32's normal range, and being a
+    // power of two it changes no rounding.  The copy is written with the scale
+    // of the residual before the previous pass (rms 1 at that pass, so the
+    // reduction of one pass below it); it is rewritten when its rms has left
+    // [2^-40, 2^40].  With mixed_rhs16 the pass reads an FP16 copy brought to
+    // about unit rms by a further power of two, which bounds what one pass can
+    // reduce.
     const bool rhs16 = ctx->cfg.mixed_rhs16 != 0;
     const double floor_rho = rhs16 ? std::max(ctx->cfg.srj_reduction, kRhs16Floor) : ctx->cfg.srj_reduction;
+    const double sqrt_n = std::sqrt((double)ctx->g.n);
+    auto unit_scale = [&](double rms) {  // power of two nearest 1/rms (rms > 0, finite)
+        return std::ldexp(1.0, (int)std::lround(-std::log2(rms)));
+    };
+    double r32_scale = 1.0;  // ctx->r32 holds r32_scale * r
     auto pass = [&]() -> stp_status {
         float* cur = ctx->e0;
         float* oth = ctx->e1;
@@ -415,20 +427,28 @@ stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, in
         const long long count = (long long)cyc.size() * inner;
         sweeps += count;
         stp_status r2;
-        // unit-rms scaling: every element is at most sqrt(n) (< FP16's 65504 for
-        // n < 4e9); a residual too small for an FP32 scale takes the FP32 path
-        const double scale = rn > 0.0 ? std::sqrt((double)ctx->g.n) / rn : 0.0;
-        if (rhs16 && std::isfinite(rn) && scale > 0.0 && std::isfinite((float)scale)) {
-            CHK(half_scaled(ctx->r16, ctx->r32, ctx->g.n, (float)scale, ctx->s));
+        const double rms = rn / sqrt_n;  // of the FP64 residual r
+        const bool scalable = rms > 0.0 && std::isfinite(rms);
+        if (scalable && !(r32_scale * rms >= 0x1p-40 && r32_scale * rms <= 0x1p40)) {
+            r32_scale = unit_scale(rms);
+            CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s, r32_scale));
+        }
+        if (rhs16 && scalable) {
+            // every element of the FP16 copy is at most about sqrt(n) (below
+            // FP16's 65504 for n < 2e9)
+            const double t = unit_scale(r32_scale * rms);
+            CHK(half_scaled(ctx->r16, ctx->r32, ctx->g.n, (float)t, ctx->s));
             r2 = timed_sweeps<float, _Float16>(ctx, ctx->r16, &cur, &oth, cyc, count, st);
             if (r2 != STP_OK) return r2;
-            CHK(add_correction_scaled(p, cur, ctx->g.n, 1.0 / scale, ctx->s));
+            CHK(add_correction_scaled(p, cur, ctx->g.n, 1.0 / (r32_scale * t), ctx->s));
         } else {
             r2 = timed_sweeps<float>(ctx, ctx->r32, &cur, &oth, cyc, count, st);
             if (r2 != STP_OK) return r2;
-            CHK(add_correction(p, cur, ctx->g.n, ctx->s));
+            if (r32_scale == 1.0) CHK(add_correction(p, cur, ctx->g.n, ctx->s));
+            else CHK(add_correction_scaled(p, cur, ctx->g.n, 1.0 / r32_scale, ctx->s));
         }
-        CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s));
+        if (scalable) r32_scale = unit_scale(rms);
+        CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s, r32_scale));
         r2 = readback(ctx);
         if (r2 != STP_OK) return r2;
         r2 = timed_flush(ctx, st);
@@ -443,7 +463,7 @@ stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, in
     int corrections = 0;
     auto correct = [&]() -> stp_status {
         CHK(ctx->net->predict(b, p, ctx->ptmp));
-        CHK(residual(ctx->g, b, ctx->ptmp, ctx->r32, ctx->part, ctx->res, ctx->s));
+        CHK(residual(ctx->g, b, ctx->ptmp, ctx->r32, ctx->part, ctx->res, ctx->s, r32_scale));
         stp_status r2 = readback(ctx);
         if (r2 != STP_OK) return r2;
         const double rg = std::sqrt(ctx->host[RES_R2]);
@@ -452,7 +472,7 @@ stp_status solve_mixed(stp_ctx* ctx, const double* b, double* p, double rtol, in
             rn = rg;
             ++corrections;
         } else {
-            CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s));
+            CHK(residual(ctx->g, b, p, ctx->r32, ctx->part, ctx->res, ctx->s, r32_scale));
         }
         return STP_OK;
     };

@@ -110,12 +110,13 @@ hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wt
 hipError_t relax(const Geo& g, const _Float16* b, const float* p, float* out, const Weights& wts, int nfused,
                  hipStream_t s);
 
-// r = b - L p (FP64); sum r^2 -> res[RES_R2]; optional FP32 copy of r.
+// r = b - L p (FP64); sum r^2 -> res[RES_R2]; optional FP32 copy of
+// r32_scale * r (r32_scale a power of two, so the copy rounds r alone).
 hipError_t residual(const Geo& g, const double* b, const double* p, float* r32, double* part, double* res,
-                    hipStream_t s);
+                    hipStream_t s, double r32_scale = 1.0);
 hipError_t add_correction(double* p, const float* e, long long n, hipStream_t s);
 hipError_t add_correction_scaled(double* p, const float* e, long long n, double inv_scale, hipStream_t s);
-// dst = FP16(scale * r)
+// dst = FP16(scale * r), scale a power of two
 hipError_t half_scaled(_Float16* dst, const float* r, long long n, float scale, hipStream_t s);
 
 hipError_t project(const Geo& g, const double* p, double* u, double* v, double* w, double dt, hipStream_t s);

@@ -268,7 +268,8 @@ __global__ void k_add_correction(double* __restrict__ p, const float* __restrict
         p[q] += (double)e[q];
 }
 
-// p += e / scale: the correction of a pass whose right-hand side was scaled by `scale`
+// p += e / scale: the correction of a pass whose right-hand side was scaled by
+// `scale` (a power of two, so the product is exact)
 __global__ void k_add_correction_scaled(double* __restrict__ p, const float* __restrict__ e, long long n,
                                         double inv_scale)
 {
@@ -276,7 +277,8 @@ __global__ void k_add_correction_scaled(double* __restrict__ p, const float* __r
         p[q] += inv_scale * (double)e[q];
 }
 
-// FP16 copy of scale * r (round to nearest); scale brings the rms of r to 1
+// FP16 copy of scale * r (round to nearest); scale, a power of two, brings the
+// rms of r to about 1
 __global__ void k_half_scaled(_Float16* __restrict__ d, const float* __restrict__ r, long long n, float scale)
 {
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
@@ -818,7 +820,7 @@ __global__ __launch_bounds__(256) void k_div(Geo g, int kchunk, const double* __
 // r = b - L_p p in FP64 with partial sums of r^2; optional FP32 copy of r.
 __global__ __launch_bounds__(256) void k_residual(Geo g, int kchunk, const double* __restrict__ b,
                                                   const double* __restrict__ p, float* __restrict__ r32,
-                                                  double* __restrict__ part)
+                                                  double r32_scale, double* __restrict__ part)
 {
     __shared__ double lds[16];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -836,7 +838,7 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, int kchunk, const doubl
                                (p[at(g, i, jm, k)] + p[at(g, i, jp, k)] - 2.0 * pc) * g.idy2 +
                                ((pt - pc) + (pb - pc)) * g.idz2;
             const double r = b[c] - lap;
-            if (r32) r32[c] = (float)r;
+            if (r32) r32[c] = (float)(r32_scale * r);
             acc += r * r;
             pb = pc;
             pc = pt;
@@ -1109,10 +1111,10 @@ hipError_t sum_into(const double* a, long long n, double* part, double* res, int
 }
 
 hipError_t residual(const Geo& g, const double* b, const double* p, float* r32, double* part, double* res,
-                    hipStream_t s)
+                    hipStream_t s, double r32_scale)
 {
     const March m = march_shape(g, 2048);
-    hipLaunchKernelGGL(k_residual, m.grid, m.block, 0, s, g, m.kchunk, b, p, r32, part);
+    hipLaunchKernelGGL(k_residual, m.grid, m.block, 0, s, g, m.kchunk, b, p, r32, r32_scale, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize(part, m.nblocks(), 1, 0u, res, RES_R2, s);

@@ -1,7 +1,10 @@
 """GPU parity of the learned warm-start network (BF16 MFMA kernels, FP32
 accumulation) against the FP64 oracle that rounds to bfloat16 at the same
-points, through the C ABI: forward output, loss, every parameter gradient,
-Adam updates, and the warm start inside a time step."""
+points, through the C ABI: forward output, loss, every parameter gradient
+(relative L2 <= 2e-3 and cosine >= 0.9999; BF16 x BF16 products are exact in
+FP32, so the two differ by accumulation order and the re-rounding it can
+flip), Adam updates, the coarse-correction proposal, and the warm start
+inside a time step."""
 import math
 
 import numpy as np
@@ -66,8 +69,9 @@ def test_forward_matches_oracle(gpu, g):
     ch.net_predict(to_dev(torch, b), to_dev(torch, p_prev), out)
     got = out.cpu().numpy()
     err = rel_l2(got - p_prev, ref - p_prev)
-    print(f"  increment rel_l2 {err:.2e}, cos {cosine(got - p_prev, ref - p_prev):.6f}")
-    assert err <= 5e-3
+    cos = cosine((got - p_prev).ravel(), (ref - p_prev).ravel())
+    print(f"  increment rel_l2 {err:.2e}, cos {cos:.8f}")
+    assert err <= 2e-3 and cos >= 0.9999
 
 
 @pytest.mark.parametrize("g", GRIDS)
@@ -86,13 +90,13 @@ def test_gradients_match_oracle(gpu, g):
     x, s = onet.normalise(b, p_prev, oracle.lap_p(P, p_prev), oracle.diag_d(P))
     loss_ref, g_ref, _ = onet.loss_and_grads(p, x, (p_next - p_prev) / s, round_bf16=True)
     loss = ch.net_train_step(to_dev(torch, b), to_dev(torch, p_prev), to_dev(torch, p_next), 0.0)
-    assert loss == pytest.approx(loss_ref, rel=5e-3)
+    assert loss == pytest.approx(loss_ref, rel=2e-3)
     got = from_flat(grads.cpu().numpy(), layout)
     for k in g_ref:
         e = rel_l2(got[k], g_ref[k])
         c = cosine(got[k].ravel(), g_ref[k].ravel())
-        print(f"  {k}: rel_l2 {e:.2e} cos {c:.6f}")
-        assert e <= 2e-2 and c >= 0.999, k
+        print(f"  {k}: rel_l2 {e:.2e} cos {c:.8f}")
+        assert e <= 2e-3 and c >= 0.9999, k
     # weights untouched with lr = 0, padding stays zero
     assert padding_is_zero(grads.cpu().numpy(), layout)
     np.testing.assert_array_equal(params.cpu().numpy(), to_flat(p, layout, params.numel()))
@@ -202,3 +206,93 @@ def test_nan_weights_fall_back_to_plain_solve(gpu):
         ch.close()
     for name, a, b in zip("uvwp", out[0], out[1]):
         assert torch.equal(a, b), name
+
+
+# several k_conv_march tiles, ragged tile edges and several z-chunks at every
+# level: 136 x 72 x 64, 68 x 36 x 32 and 34 x 18 x 16 against 32 x 16 (and
+# 32 x 8) tiles and chunks of at least 8 planes
+GRID_MULTI = (136, 72, 64, 4.0, 2.0, 2.0)
+
+
+def test_forward_loss_gradients_multi_tile(gpu):
+    """Forward increment, loss and every parameter gradient on a grid whose
+    every level spans several tiles and z-chunks: relative L2 <= 2e-3 and
+    cosine >= 0.9999 against the oracle rounding to BF16 at the same points."""
+    import torch
+    g = GRID_MULTI
+    print(f"net multi-tile grid={g[:3]}", flush=True)
+    ch, layout, params, grads = make(g)
+    p = onet.init_params(seed=21)
+    r = inputs.rng(22)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = 0.05 * r.standard_normal(p[k].shape)
+    upload(ch, params, p, layout)
+    b, p_prev, p_next = sample(g, 23)
+    P = oracle.make_params(*g)
+    lap = oracle.lap_p(P, p_prev)
+    ref = onet.predict(p, b, p_prev, lap, oracle.diag_d(P), round_bf16=True)
+    out = torch.zeros_like(to_dev(torch, b))
+    ch.net_predict(to_dev(torch, b), to_dev(torch, p_prev), out)
+    got = out.cpu().numpy()
+    e, c = rel_l2(got - p_prev, ref - p_prev), cosine((got - p_prev).ravel(), (ref - p_prev).ravel())
+    print(f"  forward increment rel_l2 {e:.2e} cos {c:.8f}", flush=True)
+    assert e <= 2e-3 and c >= 0.9999
+    x, s = onet.normalise(b, p_prev, lap, oracle.diag_d(P))
+    loss_ref, g_ref, _ = onet.loss_and_grads(p, x, (p_next - p_prev) / s, round_bf16=True)
+    loss = ch.net_train_step(to_dev(torch, b), to_dev(torch, p_prev), to_dev(torch, p_next), 0.0)
+    print(f"  loss {loss:.8e} oracle {loss_ref:.8e}", flush=True)
+    assert loss == pytest.approx(loss_ref, rel=2e-3)
+    got_g = from_flat(grads.cpu().numpy(), layout)
+    worst = []
+    for k in g_ref:
+        e = rel_l2(got_g[k], g_ref[k])
+        c = cosine(got_g[k].ravel(), g_ref[k].ravel())
+        print(f"  {k}: rel_l2 {e:.2e} cos {c:.8f}", flush=True)
+        worst.append((k, e, c))
+    for k, e, c in worst:
+        assert e <= 2e-3 and c >= 0.9999, (k, e, c)
+
+
+def test_coarse_correction_proposal_matches_oracle(gpu):
+    """The learned coarse correction's proposal p + s_r y(r, p), taken on an
+    intermediate iterate of a mixed solve (one FP32 defect-correction pass of
+    an LES step's Poisson problem, with the shipped weights), against the
+    oracle network's proposal for the same iterate: the increments agree to
+    2e-3 relative L2 (cosine 0.9999), and so do their FP64 residual norms."""
+    import os
+    import torch
+    from paper_1511_07800_amd import Channel, STP_MIXED, STP_ENOCONV, STP_P, STP_RHS, warmstart
+    g = (128, 64, 48, 4 * math.pi, 2 * math.pi, 2.0)
+    nx, ny, nz, lx, ly, lz = g
+    u, v, w = inputs.channel_state(nx, ny, nz, lz, 1 / 180, -1.0, noise=0.1, seed=61)
+    ch = Channel(*g, nu=1 / 180, dpdx=-1.0, dt=4e-5, les=1, precision=STP_MIXED, poisson_rtol=1e-8,
+                 poisson_maxit=100, srj_adaptive=1, srj_reduction=1e-4)
+    ch.net_init(training=False)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    warmstart.load_weights(ch, os.path.join(root, "paper_1511_07800_amd", "weights", "warmstart_les512_all.npy"))
+    load_state(ch, u, v, w)
+    ch.step(2)
+    p_prev = ch.field(STP_P).clone()
+    ch.step(1)
+    b = ch.field(STP_RHS).clone()
+    p_it = p_prev.clone()
+    st, rc = ch.poisson_solve(b, p_it, 1e-12, 1, allow=(STP_ENOCONV,))
+    assert rc == STP_ENOCONV and st["outer"] == 1
+    prop = torch.zeros_like(b)
+    ch.net_predict(b, p_it, prop)
+    r_gpu = ch.residual_norm(b, prop)
+    params, _ = ch.net_params()
+    pw = from_flat(params.cpu().numpy(), ch.net_layout())
+    P = oracle.make_params(*g)
+    bn, pn = b.cpu().numpy(), p_it.cpu().numpy()
+    ref = onet.predict(pw, bn, pn, oracle.lap_p(P, pn), oracle.diag_d(P), round_bf16=True)
+    got = prop.cpu().numpy()
+    e, c = rel_l2(got - pn, ref - pn), cosine((got - pn).ravel(), (ref - pn).ravel())
+    r_ref = math.sqrt(oracle.residual(P, ref, bn)[1])
+    r_it = math.sqrt(oracle.residual(P, pn, bn)[1])
+    print(f"proposal: increment rel_l2 {e:.2e} cos {c:.8f}; residual of the iterate {r_it:.4e}, "
+          f"of the proposal {r_gpu:.4e} (oracle {r_ref:.4e})", flush=True)
+    assert e <= 2e-3 and c >= 0.9999
+    assert r_gpu == pytest.approx(r_ref, rel=2e-3)
+    ch.close()

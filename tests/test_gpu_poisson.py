@@ -179,6 +179,42 @@ def test_mixed_solve_against_fp64_oracle(gpu, g, rhs16):
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("rhs16", [0, 1])
+def test_mixed_solve_scales_with_the_right_hand_side(gpu, rhs16):
+    """The mixed solve's FP32 (and FP16) passes read a power-of-two multiple
+    of the residual brought to about unit rms, so scaling b by a power of two
+    scales the whole solve exactly: with b times 2^-400 (far below FP32's
+    normal range) or 2^300 (above it) the solution is the unscaled one times
+    the same factor, bit for bit, after the same passes and sweeps; with b
+    times 1e-36 and 1e30 the solve still meets the tolerance, and its
+    solution differs from the unscaled one by no more than two solutions of
+    relative residual 1e-8 can (2e-8 / kappa_min relative)."""
+    import torch
+    from paper_1511_07800_amd import STP_MIXED
+    g = (96, 40, 24, 4.0, 2.0, 2.0)
+    kmin, _ = osched.kappa_bounds(*g)
+    b = torch.from_numpy(inputs.poisson_rhs(g[0], g[1], g[2], seed=19)).cuda()
+    ch = channel(g, precision=STP_MIXED, mixed_rhs16=rhs16, srj_adaptive=1, srj_reduction=1e-4)
+    p_ref = torch.zeros_like(b)
+    st_ref, rc = ch.poisson_solve(b, p_ref, 1e-8, 50)
+    assert rc == 0 and st_ref["relres"] <= 1e-8
+    for k in (-400, 300):
+        f = math.ldexp(1.0, k)
+        p = torch.zeros_like(b)
+        st, rc = ch.poisson_solve(b * f, p, 1e-8, 50)
+        print(f"rhs16={rhs16} b*2^{k}: passes {st['outer']} sweeps {st['sweeps']} relres {st['relres']:.2e}",
+              flush=True)
+        assert rc == 0 and st["sweeps"] == st_ref["sweeps"] and st["outer"] == st_ref["outer"]
+        assert torch.equal(p * math.ldexp(1.0, -k), p_ref)
+    for f in (1e-36, 1e30):
+        p = torch.zeros_like(b)
+        st, rc = ch.poisson_solve(b * f, p, 1e-8, 50)
+        err = float((p / f - p_ref).norm() / p_ref.norm())
+        print(f"rhs16={rhs16} b*{f:g}: passes {st['outer']} relres {st['relres']:.2e} rel_l2 {err:.2e}", flush=True)
+        assert rc == 0 and st["relres"] <= 1e-8 and err <= 2e-8 / kmin
+    ch.close()
+
+
 FULL = {512: (512, 256, 192, 4 * math.pi, 2 * math.pi, 2.0), 1024: (1024, 512, 384, 4 * math.pi, 2 * math.pi, 2.0)}
 
 
