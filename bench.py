@@ -2,19 +2,23 @@
 
 One "step" is a whole time step of the hot path (eddy viscosity, explicit
 terms, Crank-Nicolson predictor, divergence, SRJ pressure solve to a fixed
-relative residual, correction, diagnostics) on the 512x256x192 LES channel
-with inputs already resident in HBM.  Prints one JSON line.
+relative residual, correction, diagnostics) on the 1024x512x384 LES channel
+(2e8 cells, the largest single-GPU workload) with inputs already resident in
+HBM.  Prints one JSON line.
 
-value  = relaxation cell-updates per second over the whole timed steps
-         (sweeps x cells / wall time of the steps, everything included).
-Also reported: LES steps/s for the mixed (FP32 sweeps, FP64 residual and
-defect correction) and plain FP64 solves at the same relative residual, for
-the mixed solve started from the extrapolated, the least-squares and the
-learned initial guesses and their combinations, the
-fields of every variant against the FP64 run's after the same steps, the
-dominant kernel's roofline (FP32 relaxation sweep, HBM-bound), a table of
-back-to-back sweep rates for every fusion depth in FP32 and FP64 beside a
-plain device copy, and the FP64 oracle's sweep rate on the host cores.
+value  = relaxation cell-updates per second over the whole timed steps of
+         the mixed solve (sweeps x cells / wall time of the steps, every
+         other part of the step included).
+Also reported: LES steps/s at the same relative residual for the plain FP64
+solve, the mixed solve (FP32 sweeps, FP64 residual and defect correction),
+the mixed solve from the least-squares guess, from the learned guess, and
+from the least-squares guess refined by the network with each pass's
+right-hand side in FP16 (more with --all-variants); per timed step the
+sweeps, the starting residual and the least-squares rank; the fields of
+every variant against the FP64 run's; the dominant kernel's roofline (FP32
+relaxation sweep, HBM-bound); a table of back-to-back sweep rates for every
+fusion depth beside a plain device copy; and the FP64 oracle on the host
+cores (1 thread and all cores).
 """
 import argparse
 import json
@@ -30,6 +34,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "pressure-relax Gcell-updates/s + %HBM peak; LES steps/s, learned vs plain"
 FIXED_CYCLES = False  # set by --fixed-cycles: repeat the 1e-3 cycle instead of sizing cycles adaptively
 PROJ_DEPTH = 8  # earlier solutions in the least-squares initial guess
+DEFAULT_WORKLOAD = "les_channel_1024x512x384"
 
 
 def parse():
@@ -39,16 +44,18 @@ def parse():
     # untimed steps: past the start-up transient of the laminar+noise start and
     # twice the least-squares history depth, so the timed steps are steady state
     ap.add_argument("--warmup", type=int, default=16)
-    ap.add_argument("--workload", default="les_channel_512x256x192")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start run")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start runs")
     ap.add_argument("--no-table", action="store_true", help="skip the sweep-rate table")
+    ap.add_argument("--all-variants", action="store_true",
+                    help="also run the extrapolated guess, the FP16 right-hand side alone, the learned coarse "
+                         "correction and the network trained at 256x128x128")
     ap.add_argument("--weights", default="warmstart_les512_all.npy",
                     help="network weights of the learned variants (file in paper_1511_07800_amd/weights)")
     ap.add_argument("--fixed-cycles", action="store_true", help="repeat the fixed 1e-3 SRJ cycle (no adaptive sizing)")
-    ap.add_argument("--sweeps", type=int, default=200, help="sweeps in the kernel roofline timing")
     ap.add_argument("--profile-fastest", action="store_true",
                     help="run only the fastest variant (least-squares guess refined by the network, each "
                          "pass's right-hand side in FP16), for a kernel trace of its steps")
@@ -70,6 +77,7 @@ def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap
                                    noise=wl.get("noise", 0.0), seed=wl.get("seed", 0))
     for k, a in enumerate((u, v, w)):
         ch.field(k).copy_(torch.from_numpy(a))
+    del u, v, w
     torch.cuda.synchronize()
     return ch
 
@@ -77,7 +85,9 @@ def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap
 def time_steps(ch, steps, warmup, label):
     """Time `steps` whole LES steps after `warmup`; also sums the in-step
     relaxation statistics (sweeps, kernel launches and their device time,
-    measured by the library with events on its stream)."""
+    measured by the library with events on its stream) and keeps, per timed
+    step, the sweeps, the starting relative residual and the least-squares
+    rank."""
     import torch
     for i in range(warmup):
         st = ch.step(1)
@@ -85,11 +95,14 @@ def time_steps(ch, steps, warmup, label):
               f"relres0 {st['poisson']['relres0']:.2e} cfl {st['cfl']:.3f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     acc = {"sweeps": 0, "launches": 0, "ms_relax": 0.0, "corrections": 0}
+    per_step = []
     t0 = time.perf_counter()
     for i in range(steps):
         st = ch.step(1)
         for k in acc:
             acc[k] += st["poisson"][k]
+        per_step.append({"sweeps": st["poisson"]["sweeps"], "relres0": float(f"{st['poisson']['relres0']:.3e}"),
+                         "proj_rank": st["proj_rank"]})
         print(f"[{label}] step {i + 1}/{steps}: sweeps {st['poisson']['sweeps']} outer {st['poisson']['outer']} "
               f"relres0 {st['poisson']['relres0']:.2e} relres {st['poisson']['relres']:.2e} "
               f"ms {st['ms_total']:.1f} (poisson {st['ms_poisson']:.1f}, sweeps {st['poisson']['ms_relax']:.1f}) "
@@ -103,7 +116,7 @@ def time_steps(ch, steps, warmup, label):
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dt, acc, st
+    return dt, acc, st, per_step
 
 
 def roofline_from_steps(n, acc, word_bytes, kernel, rhs_bytes=None):
@@ -228,29 +241,144 @@ def field_errors(got, ref):
     return {name: float((g - r).norm() / r.norm()) for name, g, r in zip("uvwp", got, ref)}
 
 
-def cpu_baseline(wl, seconds=12.0):
-    """The FP64 oracle's relaxation sweep on the host cores, on a bounded
-    sample: consecutive sweeps of the same grid (the schedule's weights in
-    order) for about `seconds` of wall time."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_sweeps(P, b, om, seconds):
+    """Consecutive oracle sweeps of the schedule's weights in order, as many
+    as about `seconds` of wall time allows (counted from one timed sweep);
+    returns (sweeps, seconds)."""
     import numpy as np
     import oracle
-    from paper_1511_07800_amd import inputs
+    t0 = time.perf_counter()
+    p = oracle.srj_cycle(P, om[:3], np.zeros_like(b), b)
+    one = (time.perf_counter() - t0) / 3
+    nsw = int(max(1, min(len(om) - 3, seconds / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.srj_cycle(P, om[3:3 + nsw], p, b)
+    return nsw, time.perf_counter() - t0
+
+
+def cpu_baseline(wl):
+    """The FP64 oracle on the host cores, on a bounded sample (about 20 s):
+    consecutive SRJ sweeps of the workload's grid with all the threads the
+    oracle's OpenMP runtime uses and with one thread, and whole oracle time
+    steps of the 32x16x16 laminar workload (rtol 1e-10) and of the 256x8x128
+    linear-instability workload (the Orr-Sommerfeld wave, rtol 1e-10)."""
+    import numpy as np
+    import oracle
+    from paper_1511_07800_amd import inputs, workloads
     nx, ny, nz = wl["nx"], wl["ny"], wl["nz"]
+    n = nx * ny * nz
     P = oracle.make_params(nx, ny, nz, wl["lx"], wl["ly"], wl["lz"])
     b = inputs.poisson_rhs(nx, ny, nz, seed=1511)
-    p = np.zeros_like(b)
     om = oracle.srj_schedule(nx, ny, nz, wl["lx"], wl["ly"], wl["lz"])
-    p = oracle.srj_sweep(P, om[0], p, b)
-    nsw = 0
+    threads = oracle.set_threads(0)
+    nsw, t_all = oracle_sweeps(P, b, om, 8.0)
+    oracle.set_threads(1)
+    nsw1, t_one = oracle_sweeps(P, b, om, 8.0)
+    oracle.set_threads(threads)
+    del b
+    steps = {}
+    # whole steps at the small workloads (all threads)
+    w0 = workloads.params("laminar_poiseuille_32x16x16")
+    P0 = oracle.make_params(w0["nx"], w0["ny"], w0["nz"], w0["lx"], w0["ly"], w0["lz"], nu=w0["nu"],
+                            dpdx=w0["dpdx"], dt=w0["dt"])
+    z = np.zeros((w0["nz"], w0["ny"], w0["nx"]))
+    s0 = oracle.Solver(P0, z, z, np.zeros((w0["nz"] + 1, w0["ny"], w0["nx"])), rtol=w0["poisson_rtol"])
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds and nsw < 10000:
-        p = oracle.srj_sweep(P, om[nsw % len(om)], p, b)
-        nsw += 1
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(nsw * nx * ny * nz / dt / 1e9, 4), "unit": "Gcell-updates/s", "cores": cores,
-            "kind": "oracle", "sample": f"{nsw} consecutive FP64 SRJ sweeps of the {nx}x{ny}x{nz} grid "
-                                        f"({dt:.1f} s, OpenMP over z-planes)"}
+    for _ in range(20):
+        s0.step()
+    steps["laminar_poiseuille_32x16x16"] = {"ms_per_step": round(1e3 * (time.perf_counter() - t0) / 20, 3),
+                                            "steps": 20}
+    w1 = workloads.params("linear_instability_256x8x128")
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _ts import ts_initial_state
+    u, v, w, _, g1 = ts_initial_state(w1["nx"], w1["ny"], w1["nz"], w1["lx"], w1["lz"], 1 / w1["nu"],
+                                      w1["ts_alpha"], w1["ts_amplitude"])
+    P1 = oracle.make_params(w1["nx"], w1["ny"], w1["nz"], w1["lx"], w1["ly"], w1["lz"], nu=w1["nu"], dpdx=g1,
+                            dt=w1["dt"])
+    s1 = oracle.Solver(P1, u, v, w, rtol=w1["poisson_rtol"])
+    s1.step()  # the first solve starts from p = 0
+    t0 = time.perf_counter()
+    st1 = [s1.step() for _ in range(3)]
+    steps["linear_instability_256x8x128"] = {"ms_per_step": round(1e3 * (time.perf_counter() - t0) / 3, 1),
+                                             "steps": 3, "cycles_per_step": [s["poisson_cycles"] for s in st1],
+                                             "sweeps_per_cycle": len(s1.omega)}
+    return {"value": round(nsw * n / t_all / 1e9, 4), "unit": "Gcell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{nsw} consecutive FP64 SRJ sweeps of the {nx}x{ny}x{nz} grid on {threads} threads "
+                      f"({t_all:.1f} s, OpenMP over z-planes); also {nsw1} on 1 thread and whole oracle steps "
+                      f"of the two small workloads",
+            "one_thread": {"value": round(nsw1 * n / t_one / 1e9, 4), "unit": "Gcell-updates/s", "sweeps": nsw1,
+                           "seconds": round(t_one, 2)},
+            "nproc": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count(),
+            "cpu_model": cpu_model(), "oracle_steps": steps,
+            "paper_context": "Fionn (ICHEC), 24-core nodes, 288x126x120 LES: 3.67 s per step on 24 cores, "
+                             "0.187 s on 1008 cores (the paper's strong-scaling table)"}
+
+
+VARIANTS = [
+    # name, precision, options; the learned variants load the network weights
+    ("mixed", "mixed", {}),
+    ("lsq_mixed", "mixed", {"proj_depth": PROJ_DEPTH}),
+    ("learned_mixed", "mixed", {"learned": True}),
+    ("learned_lsq_mixed_rhs16", "mixed", {"learned": True, "proj_depth": PROJ_DEPTH, "rhs16": 1}),
+    ("fp64", "fp64", {}),
+]
+EXTRA_VARIANTS = [
+    ("extrap_mixed", "mixed", {"extrap_order": 2}),
+    ("mixed_rhs16", "mixed", {"rhs16": 1}),
+    ("lsq_mixed_rhs16", "mixed", {"proj_depth": PROJ_DEPTH, "rhs16": 1}),
+    ("learned_lsq_mixed", "mixed", {"learned": True, "proj_depth": PROJ_DEPTH}),
+    ("learned_mixed_correction", "mixed", {"learned": True, "correction": 1}),
+    ("learned_extrap_mixed_correction", "mixed", {"learned": True, "extrap_order": 2, "correction": 1}),
+    ("learned_mixed_trained_256x128x128", "mixed", {"learned": True, "weights": "warmstart_les.npy"}),
+]
+
+
+def run_variant(wl, args, name, precision, opt):
+    import torch
+    from paper_1511_07800_amd import STP_FP64, STP_MIXED, STP_WS_LEARNED, STP_WS_PREV, warmstart
+    learned = opt.get("learned", False)
+    ch = make_channel(wl, STP_MIXED if precision == "mixed" else STP_FP64, args.rtol,
+                      warm_start=STP_WS_LEARNED if learned else STP_WS_PREV,
+                      learned_correction=opt.get("correction", 0), extrap_order=opt.get("extrap_order", 0),
+                      proj_depth=opt.get("proj_depth", 0), rhs16=opt.get("rhs16", 0))
+    weights = None
+    if learned:
+        ch.net_init(training=False)
+        weights = os.path.join(ROOT, "paper_1511_07800_amd", "weights", opt.get("weights", args.weights))
+        warmstart.load_weights(ch, weights)
+    t, acc, st, per_step = time_steps(ch, args.steps, args.warmup, name)
+    n = wl["nx"] * wl["ny"] * wl["nz"]
+    out = {"steps_per_s": round(args.steps / t, 4), "ms_per_step": round(1e3 * t / args.steps, 2),
+           "sweeps_per_step": acc["sweeps"] / args.steps,
+           "gcell_updates_per_s": round(acc["sweeps"] * n / t / 1e9, 2), "warmup": args.warmup,
+           "per_step": per_step}
+    if learned:
+        out.update({"ms_net_last": round(st["ms_net"], 2), "relres_prev_last": st["relres_prev"],
+                    "relres_learned_last": st["relres_learned"], "weights": os.path.relpath(weights, ROOT)})
+    if opt.get("proj_depth"):
+        out.update({"proj_depth": opt["proj_depth"], "relres_lsq_last": st["relres_proj"]})
+    if opt.get("correction"):
+        out["corrections_per_step"] = acc["corrections"] / args.steps
+    if precision == "fp64":
+        out["relax_kernel"] = roofline_from_steps(n, acc, 8, "k_relax_fused<double,double,4,16>")
+    elif opt.get("rhs16"):
+        out["relax_kernel"] = roofline_from_steps(n, acc, 4, "k_relax_fused<float,_Float16,4,8>", rhs_bytes=2)
+    f = fields_of(ch)
+    ch.close()
+    del ch
+    torch.cuda.empty_cache()
+    return out, acc, t, f
 
 
 def main():
@@ -262,7 +390,7 @@ def main():
               "decomposition is a design note, not an implementation.", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_1511_07800_amd import STP_MIXED, STP_FP64, workloads
+    from paper_1511_07800_amd import STP_MIXED, workloads
     torch.cuda.set_device(0)
     wl = workloads.params(args.workload)
     n = wl["nx"] * wl["ny"] * wl["nz"]
@@ -274,124 +402,36 @@ def main():
         ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED, proj_depth=PROJ_DEPTH, rhs16=1)
         ch.net_init(training=False)
         warmstart.load_weights(ch, os.path.join(ROOT, "paper_1511_07800_amd", "weights", args.weights))
-        t, acc, _ = time_steps(ch, args.steps, args.warmup, "learned+lsq+mixed(rhs16)")
-        print(json.dumps({"variant": "learned+lsq+mixed(rhs16)", "warmup": args.warmup, "steps": args.steps,
-                          "ms_per_step": round(1e3 * t / args.steps, 2),
-                          "sweeps_per_step": acc["sweeps"] / args.steps}), flush=True)
+        t, acc, _, per_step = time_steps(ch, args.steps, args.warmup, "learned+lsq+mixed(rhs16)")
+        print(json.dumps({"variant": "learned+lsq+mixed(rhs16)", "workload": args.workload, "warmup": args.warmup,
+                          "steps": args.steps, "ms_per_step": round(1e3 * t / args.steps, 2),
+                          "sweeps_per_step": acc["sweeps"] / args.steps, "per_step": per_step}), flush=True)
         return
 
-    ch = make_channel(wl, STP_MIXED, args.rtol)
-    t_mixed, acc_mixed, st_mixed = time_steps(ch, args.steps, args.warmup, "mixed")
-    f_mixed = fields_of(ch)
-    ch.close()
-    del ch
-    torch.cuda.empty_cache()
-
-    # the same with the guess extrapolated in time from the last solutions
-    ch = make_channel(wl, STP_MIXED, args.rtol, extrap_order=2)
-    t_ex, acc_ex, _ = time_steps(ch, args.steps, args.warmup, "extrap+mixed")
-    extrap = {"steps_per_s": round(args.steps / t_ex, 4), "ms_per_step": round(1e3 * t_ex / args.steps, 2),
-              "sweeps_per_step": acc_ex["sweeps"] / args.steps}
-    f_extrap = fields_of(ch)
-    ch.close()
-    del ch
-    torch.cuda.empty_cache()
-
-    # least-squares guess from the last 8 solutions
-    ch = make_channel(wl, STP_MIXED, args.rtol, proj_depth=PROJ_DEPTH)
-    t_ls, acc_ls, st_ls = time_steps(ch, args.steps, args.warmup, "lsq+mixed")
-    lsq = {"steps_per_s": round(args.steps / t_ls, 4), "ms_per_step": round(1e3 * t_ls / args.steps, 2),
-           "sweeps_per_step": acc_ls["sweeps"] / args.steps, "proj_depth": PROJ_DEPTH,
-           "relres_prev_last": st_ls["relres_prev"], "relres_lsq_last": st_ls["relres_proj"]}
-    f_lsq = fields_of(ch)
-    ch.close()
-    del ch
-    torch.cuda.empty_cache()
-
-    # the mixed solve with each pass's right-hand side stored in FP16, from p^n and from the least-squares guess
-    def run_rhs16(label, **kw):
-        ch = make_channel(wl, STP_MIXED, args.rtol, rhs16=1, **kw)
-        t, acc, st = time_steps(ch, args.steps, args.warmup, label)
-        out = {"steps_per_s": round(args.steps / t, 4), "ms_per_step": round(1e3 * t / args.steps, 2),
-               "sweeps_per_step": acc["sweeps"] / args.steps, "outer_last": st["poisson"]["outer"],
-               "relax_kernel": roofline_from_steps(n, acc, 4, "k_relax_fused<float,_Float16,4,8>", rhs_bytes=2)}
-        f = fields_of(ch)
-        ch.close()
-        torch.cuda.empty_cache()
-        return out, f
-    mixed16, f_mixed16 = run_rhs16("mixed(rhs16)")
-    lsq16, f_lsq16 = run_rhs16("lsq+mixed(rhs16)", proj_depth=PROJ_DEPTH)
-
-    fp64 = None
-    f_fp64 = None
-    errors = {}
-    if not args.no_fp64:
-        ch = make_channel(wl, STP_FP64, args.rtol)
-        t64, acc64, _ = time_steps(ch, args.steps, args.warmup, "fp64")
-        f_fp64 = fields_of(ch)
-        errors["mixed"] = field_errors(f_mixed, f_fp64)
-        errors["extrap+mixed"] = field_errors(f_extrap, f_fp64)
-        errors["lsq+mixed"] = field_errors(f_lsq, f_fp64)
-        errors["mixed(rhs16)"] = field_errors(f_mixed16, f_fp64)
-        errors["lsq+mixed(rhs16)"] = field_errors(f_lsq16, f_fp64)
-        fp64 = {"steps_per_s": round(args.steps / t64, 4), "ms_per_step": round(1e3 * t64 / args.steps, 2),
-                "sweeps_per_step": acc64["sweeps"] / args.steps,
-                "gcell_updates_per_s": round(acc64["sweeps"] * n / t64 / 1e9, 2),
-                "relax_kernel": roofline_from_steps(n, acc64, 8, "k_relax_fused<double,4,16>")}
-        ch.close()
-        del ch
-        torch.cuda.empty_cache()
-
-    learned = None
-    learned_256 = None
-    learned_cc = None
-    learned_ex = None
-    learned_all = None
-    learned_ls = None
-    learned_ls_cc = None
-    learned_ls16 = None
-    if not args.no_learned:
-        from paper_1511_07800_amd import STP_WS_LEARNED, warmstart
-
-        def run_learned(weights, label, correction=0, extrap_order=0, proj_depth=0, rhs16=0):
-            ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED, learned_correction=correction,
-                              extrap_order=extrap_order, proj_depth=proj_depth, rhs16=rhs16)
-            ch.net_init(training=False)
-            warmstart.load_weights(ch, weights)
-            tl, accl, stl = time_steps(ch, args.steps, args.warmup, label)
-            out = {"steps_per_s": round(args.steps / tl, 4), "ms_per_step": round(1e3 * tl / args.steps, 2),
-                   "sweeps_per_step": accl["sweeps"] / args.steps, "ms_net_last": round(stl["ms_net"], 2),
-                   "relres_prev_last": stl["relres_prev"], "relres_learned_last": stl["relres_learned"],
-                   "relres_extrap_last": stl["relres_extrap"] if extrap_order else None,
-                   "relres_lsq_last": stl["relres_proj"] if proj_depth else None,
-                   "corrections_per_step": accl["corrections"] / args.steps,
-                   "weights": os.path.relpath(weights, ROOT)}
-            if f_fp64 is not None:
-                errors[label] = field_errors(fields_of(ch), f_fp64)
-            ch.close()
-            torch.cuda.empty_cache()
-            return out
-
-        wdir = os.path.join(ROOT, "paper_1511_07800_amd", "weights")
-        learned = run_learned(os.path.join(wdir, args.weights), "learned+mixed")
-        learned_256 = run_learned(os.path.join(wdir, "warmstart_les.npy"), "learned(256-trained)+mixed")
-        learned_cc = run_learned(os.path.join(wdir, args.weights), "learned+correction+mixed", correction=1)
-        learned_ex = run_learned(os.path.join(wdir, args.weights), "learned+extrap+mixed", extrap_order=2)
-        learned_all = run_learned(os.path.join(wdir, args.weights), "learned+extrap+correction+mixed",
-                                  correction=1, extrap_order=2)
-        learned_ls = run_learned(os.path.join(wdir, args.weights), "learned+lsq+mixed", proj_depth=PROJ_DEPTH)
-        learned_ls_cc = run_learned(os.path.join(wdir, args.weights), "learned+lsq+correction+mixed",
-                                    correction=1, proj_depth=PROJ_DEPTH)
-        learned_ls16 = run_learned(os.path.join(wdir, args.weights), "learned+lsq+mixed(rhs16)",
-                                   proj_depth=PROJ_DEPTH, rhs16=1)
-
-    roof = roofline_from_steps(n, acc_mixed, 4, "k_relax_fused<float,4,8>")
-    roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
-    del f_mixed, f_extrap, f_lsq, f_mixed16, f_lsq16, f_fp64
+    todo = [v for v in VARIANTS if not (args.no_fp64 and v[1] == "fp64")
+            and not (args.no_learned and v[2].get("learned"))]
+    if args.all_variants:
+        todo = todo[:-1] + [v for v in EXTRA_VARIANTS if not (args.no_learned and v[2].get("learned"))] + todo[-1:]
+    results, fields = {}, {}
+    acc_mixed = t_mixed = None
+    for name, precision, opt in todo:
+        out, acc, t, f = run_variant(wl, args, name, precision, opt)
+        results[name] = out
+        fields[name] = f
+        if name == "mixed":
+            acc_mixed, t_mixed = acc, t
+            roof = roofline_from_steps(n, acc, 4, "k_relax_fused<float,float,4,8>")
+            roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
+    errors = None
+    if "fp64" in fields:
+        errors = {k: field_errors(f, fields["fp64"]) for k, f in fields.items() if k != "fp64"}
+    del fields
     torch.cuda.empty_cache()
     table = None if args.no_table else relax_sweep_table(wl)
     cpu = None if args.no_cpu else cpu_baseline(wl)
 
+    fp64_rate = results["fp64"]["steps_per_s"] if "fp64" in results else None
+    steps_per_s = {k: v["steps_per_s"] for k, v in results.items()}
     value = acc_mixed["sweeps"] * n / t_mixed / 1e9
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Gcell-updates/s", "n_gpus": 1,
@@ -401,45 +441,12 @@ def main():
         "config": {"workload": args.workload, "grid": [wl["nx"], wl["ny"], wl["nz"]], "precision": "mixed",
                    "poisson_rtol": args.rtol, "dt": wl["dt"], "les": wl["les"], "init": "laminar+10% noise",
                    "srj_cycles": "fixed 1e-3" if FIXED_CYCLES else "adaptive"},
-        "les_steps_per_s": {"mixed": round(args.steps / t_mixed, 4), "fp64": fp64["steps_per_s"] if fp64 else None,
-                            "extrap_mixed": extrap["steps_per_s"],
-                            "lsq_mixed": lsq["steps_per_s"],
-                            "mixed_rhs16": mixed16["steps_per_s"],
-                            "lsq_mixed_rhs16": lsq16["steps_per_s"],
-                            "learned_mixed": learned["steps_per_s"] if learned else None,
-                            "learned_mixed_correction": learned_cc["steps_per_s"] if learned_cc else None,
-                            "learned_extrap_mixed": learned_ex["steps_per_s"] if learned_ex else None,
-                            "learned_extrap_mixed_correction": learned_all["steps_per_s"] if learned_all else None,
-                            "learned_lsq_mixed": learned_ls["steps_per_s"] if learned_ls else None,
-                            "learned_lsq_mixed_correction": learned_ls_cc["steps_per_s"] if learned_ls_cc else None,
-                            "learned_lsq_mixed_rhs16": learned_ls16["steps_per_s"] if learned_ls16 else None},
-        "sweeps_per_step": {"mixed": acc_mixed["sweeps"] / args.steps,
-                            "fp64": fp64["sweeps_per_step"] if fp64 else None,
-                            "extrap_mixed": extrap["sweeps_per_step"],
-                            "lsq_mixed": lsq["sweeps_per_step"],
-                            "mixed_rhs16": mixed16["sweeps_per_step"],
-                            "lsq_mixed_rhs16": lsq16["sweeps_per_step"],
-                            "learned_mixed": learned["sweeps_per_step"] if learned else None,
-                            "learned_mixed_correction": learned_cc["sweeps_per_step"] if learned_cc else None,
-                            "learned_extrap_mixed": learned_ex["sweeps_per_step"] if learned_ex else None,
-                            "learned_extrap_mixed_correction": learned_all["sweeps_per_step"] if learned_all else None,
-                            "learned_lsq_mixed": learned_ls["sweeps_per_step"] if learned_ls else None,
-                            "learned_lsq_mixed_correction": learned_ls_cc["sweeps_per_step"] if learned_ls_cc else None,
-                            "learned_lsq_mixed_rhs16": learned_ls16["sweeps_per_step"] if learned_ls16 else None},
-        "fp64": fp64,
-        "extrap_mixed": extrap,
-        "lsq_mixed": lsq,
-        "mixed_rhs16": mixed16,
-        "lsq_mixed_rhs16": lsq16,
-        "learned_mixed": learned,
-        "learned_mixed_trained_256x128x128": learned_256,
-        "learned_mixed_correction": learned_cc,
-        "learned_extrap_mixed": learned_ex,
-        "learned_extrap_mixed_correction": learned_all,
-        "learned_lsq_mixed": learned_ls,
-        "learned_lsq_mixed_correction": learned_ls_cc,
-        "learned_lsq_mixed_rhs16": learned_ls16,
-        "error_vs_fp64": errors or None,
+        "les_steps_per_s": steps_per_s,
+        "les_steps_per_s_vs_fp64": ({k: round(v / fp64_rate, 3) for k, v in steps_per_s.items()}
+                                    if fp64_rate else None),
+        "sweeps_per_step": {k: v["sweeps_per_step"] for k, v in results.items()},
+        "variants": results,
+        "error_vs_fp64": errors,
         "relax_sweeps": table,
         "roofline": roof,
         "cpu_baseline": cpu,

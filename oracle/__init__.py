@@ -83,7 +83,15 @@ def lib():
         L.or_step.argtypes = [pp, dp, dp, dp, dp, ctypes.POINTER(dp), ctypes.c_int, dp, ctypes.c_int,
                               ctypes.c_double, ctypes.c_int, dp, dp, ctypes.POINTER(Stats)]
         L.or_step.restype = ctypes.c_int
+        L.or_srj_cycle.argtypes = [pp, dp, ctypes.c_int, dp, dp]
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_set_threads.restype = ctypes.c_int
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's plane loops (n <= 0: unchanged); returns the count in effect."""
+    return lib().or_set_threads(int(n))
 
 
 def _p(a):
@@ -117,6 +125,14 @@ def srj_sweep(P, omega, p, b):
     out = np.empty(cell_shape(P))
     lib().or_srj_sweep(ctypes.byref(P), float(omega), _p(np.ascontiguousarray(p, np.float64)),
                        _p(np.ascontiguousarray(b, np.float64)), _p(out))
+    return out
+
+
+def srj_cycle(P, omega, p, b):
+    """The sweeps omega applied to p in order (a new array; no residual test)."""
+    out = np.array(p, dtype=np.float64, order="C", copy=True)
+    om = np.ascontiguousarray(omega, np.float64)
+    lib().or_srj_cycle(ctypes.byref(P), _p(om), len(om), _p(out), _p(np.ascontiguousarray(b, np.float64)))
     return out
 
 

@@ -236,6 +236,18 @@ static void srj_cycle(const or_params* P, const double* omega, int m, double* p,
     if (cur != p) memcpy(p, cur, or_ncell(P) * sizeof(double));
 }
 
+/* p <- the m sweeps omega[0..m-1] applied in order (one cycle, no residual
+ * test), with the scratch arrays allocated once for the whole sequence. */
+void or_srj_cycle(const or_params* P, const double* omega, int m, double* p, const double* b)
+{
+    const size_t n = or_ncell(P);
+    double* q = (double*)malloc(n * sizeof(double));
+    double* lap = (double*)malloc(n * sizeof(double));
+    srj_cycle(P, omega, m, p, b, q, lap);
+    free(q);
+    free(lap);
+}
+
 /* Scheduled Relaxation Jacobi (Sec. 3.4): the M-sweep cycle omega[0..m-1]
  * is applied repeatedly; convergence is tested before the first cycle and
  * after each full cycle.  p holds the initial guess on entry and the
@@ -699,4 +711,23 @@ int or_step(const or_params* P, double* u, double* v, double* w, double* p, doub
     free(lu);
     for (int c = 0; c < 3; ++c) { free(en[c]); free(R[c]); }
     return status;
+}
+
+/* ------------------------------------------------------------ threads -- */
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the plane loops use (for timing the oracle on 1 or all cores);
+ * returns the number in effect afterwards.  n <= 0 leaves it unchanged. */
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
