@@ -224,6 +224,26 @@ stp_status stp_relax(stp_ctx* ctx, int32_t dtype, const void* b_dev, void* p_dev
 /* ||b - L_p p||_2 in FP64 for FP64 device arrays (synchronises). */
 stp_status stp_residual_norm(stp_ctx* ctx, const void* b_dev, const void* p_dev, double* norm);
 
+/* Allocation-free variant of stp_residual_norm, for callers that cannot
+ * allocate device or pinned memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  It needs no context (the
+ * grid comes as arguments: nx, ny, nz cells, domain lx, ly, lz, with the
+ * limits of stp_config), computes the same FP64 residual norm with the same
+ * kernels, and writes it to the device double *norm_dev, enqueued on stream
+ * (a hipStream_t; NULL is the null stream) without synchronising or reading
+ * anything back.  b_dev and p_dev are FP64 device arrays of nx*ny*nz values
+ * (borrowed, read).  The reduction partials live in a static scratch array
+ * of the library (512 KiB per GPU, held until the process ends); it allocates
+ * nothing and every partial is written before it is read.  Calls on one GPU
+ * share that scratch: calls that may overlap on the same GPU (different
+ * streams, or host threads) race, and the caller must order them.
+ * Returns STP_EINVAL for a null pointer, an invalid grid or one that needs
+ * more partials than the scratch holds (an x-y plane of more than 65536
+ * column tiles of 64 x 4 cells), STP_EDEVICE if the scratch address cannot be
+ * found or a launch fails; stp_last_error(NULL) then gives the reason. */
+stp_status stp_residual_norm_noalloc(int32_t nx, int32_t ny, int32_t nz, double lx, double ly, double lz,
+                                     const void* b_dev, const void* p_dev, void* norm_dev, void* stream);
+
 /* The least-squares guess of proj_depth on caller-given histories (not in the
  * paper; the paper starts each solve from the previous pressure, Sec. 3.4):
  * out = sum_i c_i x_i with c minimising ||b - sum_i c_i y_i||_2, for k (1..8)
@@ -314,7 +334,9 @@ stp_status stp_net_train_step(stp_ctx* ctx, const void* b_dev, const void* p_pre
 /* Release the context (not the caller's workspace). NULL is accepted. */
 stp_status stp_destroy(stp_ctx* ctx);
 
-/* Message for the last failure on ctx ("" if none); valid until the next call. */
+/* Message for the last failure on ctx ("" if none); valid until the next call.
+ * With ctx = NULL: the message of the last failed stp_residual_norm_noalloc
+ * call on this thread, or "null context". */
 const char* stp_last_error(const stp_ctx* ctx);
 
 #ifdef __cplusplus

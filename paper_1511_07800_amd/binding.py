@@ -93,6 +93,8 @@ def load_library():
     L.stp_relax.restype = i32
     L.stp_residual_norm.argtypes = [vp, vp, vp, ctypes.POINTER(dbl)]
     L.stp_residual_norm.restype = i32
+    L.stp_residual_norm_noalloc.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, vp, vp, vp]
+    L.stp_residual_norm_noalloc.restype = i32
     L.stp_lsq_guess.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, ctypes.POINTER(i32)]
     L.stp_lsq_guess.restype = i32
     L.stp_fields.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
@@ -127,6 +129,22 @@ def load_library():
 
 def _dptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def residual_norm_noalloc(nx, ny, nz, lx, ly, lz, b, p, out, stream=None):
+    """stp_residual_norm_noalloc: ||b - L p||_2 into the one-element float64
+    device tensor `out`, enqueued on `stream` (default: torch's current
+    stream), no context, no allocation, no synchronisation."""
+    import torch
+    for a in (b, p):
+        assert a.dtype == torch.float64 and a.is_contiguous() and a.numel() == nx * ny * nz
+    assert out.dtype == torch.float64 and out.numel() >= 1
+    st = torch.cuda.current_stream() if stream is None else stream
+    lib = load_library()
+    rc = lib.stp_residual_norm_noalloc(int(nx), int(ny), int(nz), float(lx), float(ly), float(lz), _dptr(b),
+                                       _dptr(p), _dptr(out), ctypes.c_void_p(st.cuda_stream))
+    if rc != STP_OK:
+        raise StpError(rc, f"stp_residual_norm_noalloc: {lib.stp_last_error(None).decode()}")
 
 
 class Channel:

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -74,12 +75,36 @@ stp_config effective(const stp_config& c)
     return e;
 }
 
+Geo make_geo(int nx, int ny, int nz, double lx, double ly, double lz)
+{
+    Geo g{};
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    g.plane = (long long)nx * ny;
+    g.n = g.plane * nz;
+    g.nw = g.plane * (nz + 1);
+    const double dx = lx / nx, dy = ly / ny, dz = lz / nz;
+    g.idx = 1.0 / dx; g.idy = 1.0 / dy; g.idz = 1.0 / dz;
+    g.idx2 = 1.0 / (dx * dx); g.idy2 = 1.0 / (dy * dy); g.idz2 = 1.0 / (dz * dz);
+    return g;
+}
+
+// Grid and domain checks shared by every entry point that takes a grid.
+const char* validate_grid(int nx, int ny, int nz, double lx, double ly, double lz)
+{
+    if (nx < 1 || ny < 1 || nz < 2) return "grid: need nx >= 1, ny >= 1, nz >= 2";
+    if ((long long)nx * ny * (nz + 1) > (1LL << 40)) return "grid too large";
+    if ((long long)nx * ny >= (1LL << 31)) return "grid plane too large (nx*ny >= 2^31)";
+    if (!finite_pos(lx) || !finite_pos(ly) || !finite_pos(lz)) return "domain lengths must be finite and > 0";
+    // the column-marching reductions keep up to 8 partials per workgroup in
+    // kMaxPartBlocks * 8 slots, and every z-chunk holds at least one plane
+    if ((long long)march_shape(make_geo(nx, ny, nz, lx, ly, lz), 2048).nblocks() > kMaxPartBlocks)
+        return "grid plane too large for the reductions (more than 65536 column tiles of 64 x 4)";
+    return nullptr;
+}
+
 const char* validate(const stp_config& c)
 {
-    if (c.nx < 1 || c.ny < 1 || c.nz < 2) return "grid: need nx >= 1, ny >= 1, nz >= 2";
-    if ((long long)c.nx * c.ny * (c.nz + 1) > (1LL << 40)) return "grid too large";
-    if ((long long)c.nx * c.ny >= (1LL << 31)) return "grid plane too large (nx*ny >= 2^31)";
-    if (!finite_pos(c.lx) || !finite_pos(c.ly) || !finite_pos(c.lz)) return "domain lengths must be finite and > 0";
+    if (const char* e = validate_grid(c.nx, c.ny, c.nz, c.lx, c.ly, c.lz)) return e;
     if (!finite_pos(c.nu)) return "nu must be finite and > 0";
     if (!finite_pos(c.dt)) return "dt must be finite and > 0";
     if (!std::isfinite(c.dpdx)) return "dpdx must be finite";
@@ -820,7 +845,71 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
 
 }  // namespace
 
+// ---- static scratch of the allocation-free entry point ---------------------
+// stp_residual_norm_noalloc keeps its reduction partials here instead of in a
+// context's workspace: one partial per workgroup of the residual kernel (at
+// most kMaxPartBlocks) and the reduced sum of squares after them.  Every GPU
+// the library runs on holds its own copy, 512 KiB plus a few slots, until the
+// process ends.  Host code must not pass `scratch` itself to a kernel (in
+// host code the name stands for a host-side shadow, not a device address):
+// it uses the address hipGetSymbolAddress returns on each device.
+constexpr int kScratchDoubles = kMaxPartBlocks + 32;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};  // address of `scratch` on each device, once looked up
+thread_local const char* g_noctx_err = "";  // message of the last failed context-free call
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current.
+hipError_t scratch_on_current_device(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[dev] == nullptr) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (ptr == nullptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+stp_status noctx_fail(stp_status rc, const char* msg)
+{
+    g_noctx_err = msg;
+    return rc;
+}
+
+}  // namespace
+
 extern "C" {
+
+stp_status stp_residual_norm_noalloc(int32_t nx, int32_t ny, int32_t nz, double lx, double ly, double lz,
+                                     const void* b_dev, const void* p_dev, void* norm_dev, void* stream)
+{
+    g_noctx_err = "";
+    if (!b_dev || !p_dev || !norm_dev) return noctx_fail(STP_EINVAL, "stp_residual_norm_noalloc: null pointer");
+    if (const char* e = validate_grid(nx, ny, nz, lx, ly, lz)) return noctx_fail(STP_EINVAL, e);
+    const Geo g = make_geo(nx, ny, nz, lx, ly, lz);
+    if ((long long)march_shape(g, 2048).nblocks() + 1 > kScratchDoubles)
+        return noctx_fail(STP_EINVAL, "stp_residual_norm_noalloc: grid needs more partials than the static scratch holds");
+    double* sp = nullptr;
+    if (scratch_on_current_device(&sp) != hipSuccess)
+        return noctx_fail(STP_EDEVICE, "stp_residual_norm_noalloc: no device address for the static scratch");
+    if (residual_norm_into(g, static_cast<const double*>(b_dev), static_cast<const double*>(p_dev), sp,
+                           static_cast<double*>(norm_dev), static_cast<hipStream_t>(stream)) != hipSuccess)
+        return noctx_fail(STP_EDEVICE, "stp_residual_norm_noalloc: kernel launch failed");
+    return STP_OK;
+}
 
 size_t stp_workspace_bytes(const stp_config* cfg)
 {
@@ -844,14 +933,8 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
     ctx->cfg = c;
     ctx->cfg.srj_omega = nullptr;  // copied below; the caller's array is not kept
     ctx->s = static_cast<hipStream_t>(c.stream);
-    Geo& g = ctx->g;
-    g.nx = c.nx; g.ny = c.ny; g.nz = c.nz;
-    g.plane = (long long)c.nx * c.ny;
-    g.n = g.plane * c.nz;
-    g.nw = g.plane * (c.nz + 1);
-    const double dx = c.lx / c.nx, dy = c.ly / c.ny, dz = c.lz / c.nz;
-    g.idx = 1.0 / dx; g.idy = 1.0 / dy; g.idz = 1.0 / dz;
-    g.idx2 = 1.0 / (dx * dx); g.idy2 = 1.0 / (dy * dy); g.idz2 = 1.0 / (dz * dz);
+    ctx->g = make_geo(c.nx, c.ny, c.nz, c.lx, c.ly, c.lz);
+    const Geo& g = ctx->g;
     ctx->D = 2.0 * (g.idx2 + g.idy2 + g.idz2);
     char* base = static_cast<char*>(ws);
     ctx->u = (double*)(base + L.u);
@@ -1207,7 +1290,7 @@ stp_status stp_destroy(stp_ctx* ctx)
 
 const char* stp_last_error(const stp_ctx* ctx)
 {
-    if (!ctx) return "null context";
+    if (!ctx) return g_noctx_err[0] ? g_noctx_err : "null context";
     return ctx->err.c_str();
 }
 

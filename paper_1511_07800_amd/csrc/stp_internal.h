@@ -114,6 +114,10 @@ hipError_t relax(const Geo& g, const _Float16* b, const float* p, float* out, co
 // r32_scale * r (r32_scale a power of two, so the copy rounds r alone).
 hipError_t residual(const Geo& g, const double* b, const double* p, float* r32, double* part, double* res,
                     hipStream_t s, double r32_scale = 1.0);
+// ||b - L p||_2 written to the device double *norm; part holds the partials
+// (march_shape(g, 2048).nblocks() + 1 doubles, every one written before it is read).
+hipError_t residual_norm_into(const Geo& g, const double* b, const double* p, double* part, double* norm,
+                              hipStream_t s);
 hipError_t add_correction(double* p, const float* e, long long n, hipStream_t s);
 hipError_t add_correction_scaled(double* p, const float* e, long long n, double inv_scale, hipStream_t s);
 // dst = FP16(scale * r), scale a power of two

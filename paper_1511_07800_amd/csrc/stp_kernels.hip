@@ -1120,6 +1120,22 @@ hipError_t residual(const Geo& g, const double* b, const double* p, float* r32, 
     return finalize(part, m.nblocks(), 1, 0u, res, RES_R2, s);
 }
 
+__global__ void k_sqrt_into(const double* __restrict__ x, double* __restrict__ out) { out[0] = sqrt(x[0]); }
+
+hipError_t residual_norm_into(const Geo& g, const double* b, const double* p, double* part, double* norm,
+                              hipStream_t s)
+{
+    const March m = march_shape(g, 2048);
+    const int nb = m.nblocks();
+    hipLaunchKernelGGL(k_residual, m.grid, m.block, 0, s, g, m.kchunk, b, p, (float*)nullptr, 1.0, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = finalize(part, nb, 1, 0u, part + nb, 0, s);  // sum r^2 into part[nb]
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sqrt_into, dim3(1), dim3(1), 0, s, part + nb, norm);
+    return hipGetLastError();
+}
+
 hipError_t add_correction(double* p, const float* e, long long n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_add_correction, dim3(grid1d(n)), dim3(kBlock1d), 0, s, p, e, n);

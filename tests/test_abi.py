@@ -121,3 +121,21 @@ def test_ctypes_structs_match_the_c_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_noalloc_entry_point_rejects_on_the_host():
+    """stp_residual_norm_noalloc checks its arguments before it touches the
+    device: null pointers, a bad grid and a plane too large for the static
+    scratch's partials are STP_EINVAL with a message for stp_last_error(NULL)."""
+    from paper_1511_07800_amd import load_library, STP_EINVAL
+    lib = load_library()
+    fake = ctypes.c_void_p(256)  # never dereferenced: every call below is rejected first
+    assert lib.stp_residual_norm_noalloc(8, 8, 4, 1.0, 1.0, 1.0, None, fake, fake, None) == STP_EINVAL
+    assert b"null" in lib.stp_last_error(None)
+    assert lib.stp_residual_norm_noalloc(8, 8, 1, 1.0, 1.0, 1.0, fake, fake, fake, None) == STP_EINVAL
+    assert lib.stp_residual_norm_noalloc(8, 8, 4, 1.0, -1.0, 1.0, fake, fake, fake, None) == STP_EINVAL
+    # 512 x 4096 column tiles of 64 x 4 cells: more partials than the scratch holds
+    assert lib.stp_residual_norm_noalloc(32768, 16384, 2, 1.0, 1.0, 1.0, fake, fake, fake, None) == STP_EINVAL
+    assert b"too large" in lib.stp_last_error(None)
+    # the same plane limit guards every context's reduction partials
+    assert lib.stp_workspace_bytes(ctypes.byref(cfg(nx=32768, ny=16384, nz=2))) == 0
