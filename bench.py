@@ -136,10 +136,10 @@ def roofline_from_steps(n, acc, word_bytes, kernel, rhs_bytes=None):
 
 
 def measured_traffic(nx, ny, nz, tblock):
-    """HBM bytes per launch of the relaxation kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
-    counters on a plain copy of known size); None if the summary is for
-    another kernel source, grid or fusion depth."""
+    """HBM-side bytes per launch of the FP32 relaxation kernel from the
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled
+    by the same counter on a plain copy of known size); None unless the
+    summary was taken on this kernel source, grid and fusion depth."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "relax_traffic.json")
     src = os.path.join(ROOT, "paper_1511_07800_amd", "csrc", "stp_relax.hip")
@@ -147,9 +147,10 @@ def measured_traffic(nx, ny, nz, tblock):
         return None
     rec = json.load(open(path))
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != sha or rec.get("grid") != [nx, ny, nz] or rec.get("sweeps_per_launch") != tblock:
+    entry = rec.get("grids", {}).get(f"{nx}x{ny}x{nz}")
+    if rec.get("source_sha256") != sha or entry is None or rec.get("sweeps_per_launch") != tblock:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return round(entry["hbm_bytes_per_launch"])
 
 
 def profile_kernels(wl):
@@ -422,6 +423,8 @@ def main():
             acc_mixed, t_mixed = acc, t
             roof = roofline_from_steps(n, acc, 4, "k_relax_fused<float,float,4,8>")
             roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
+            if roof["traffic"]:
+                roof["traffic_over_algorithmic"] = round(roof["traffic"] / (12.0 * n), 3)
     errors = None
     if "fp64" in fields:
         errors = {k: field_errors(f, fields["fp64"]) for k, f in fields.items() if k != "fp64"}
