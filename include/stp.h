@@ -261,6 +261,20 @@ stp_status stp_lsq_guess(stp_ctx* ctx, int32_t k, const void* const* x_dev, cons
  * (slowest first) and dtype.  STP_W has nz+1 planes. */
 stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape[3], int32_t* dtype);
 
+/* Plane averages of the current state at every height, the x-y means from
+ * which the paper's space-time averages, bulk velocity, centreline velocity
+ * and skin friction are formed (Sec. 6).  out: host array of 8 (nz + 1)
+ * doubles, out[q (nz + 1) + k]:
+ *   q = 0 <u>, 1 <v>, 2 <u^2>, 3 <v^2>, 4 <nu_T> on the cell planes
+ *       z = (k + 1/2) dz, k < nz (out[q (nz + 1) + nz] = 0);
+ *   q = 5 <w>, 6 <w^2> on the face planes z = k dz, k = 0..nz;
+ *   q = 7 <u w> on the x-z edges (i dx, k dz), k = 0..nz, with u averaged
+ *       over the planes k - 1 and k (odd ghosts beyond the walls) and w over
+ *       the columns i - 1 and i.
+ * nu_T is the eddy viscosity of the last step (computed from its starting
+ * velocity).  FP64, fixed summation order; synchronises the stream. */
+stp_status stp_plane_stats(stp_ctx* ctx, double* out);
+
 /* The relaxation cycle in use: writes min(cap, M) weights, *m = M. */
 stp_status stp_schedule(const stp_ctx* ctx, double* omega, int32_t cap, int32_t* m);
 

@@ -84,6 +84,7 @@ def lib():
                               ctypes.c_double, ctypes.c_int, dp, dp, ctypes.POINTER(Stats)]
         L.or_step.restype = ctypes.c_int
         L.or_srj_cycle.argtypes = [pp, dp, ctypes.c_int, dp, dp]
+        L.or_plane_stats.argtypes = [pp, dp, dp, dp, dp, dp]
         L.or_set_threads.argtypes = [ctypes.c_int]
         L.or_set_threads.restype = ctypes.c_int
     return _lib
@@ -236,6 +237,20 @@ def diagnostics(P, u, v, w):
     st = Stats()
     lib().or_diagnostics(ctypes.byref(P), _p(u), _p(v), _p(w), ctypes.byref(st))
     return st.as_dict()
+
+
+PLANE_STATS = ("u", "v", "uu", "vv", "nut", "w", "ww", "uw")
+
+
+def plane_stats(P, u, v, w, nut_):
+    """x-y means at every height (or_plane_stats): dict of u, v, uu, vv, nut
+    (nz cell planes) and w, ww, uw (nz + 1 face planes)."""
+    out = np.zeros(8 * (P.nz + 1))
+    lib().or_plane_stats(ctypes.byref(P), _p(np.ascontiguousarray(u, np.float64)),
+                         _p(np.ascontiguousarray(v, np.float64)), _p(np.ascontiguousarray(w, np.float64)),
+                         _p(np.ascontiguousarray(nut_, np.float64)), _p(out))
+    out = out.reshape(8, P.nz + 1)
+    return {name: (out[q, :P.nz].copy() if q < 5 else out[q].copy()) for q, name in enumerate(PLANE_STATS)}
 
 
 class Solver:

@@ -626,6 +626,40 @@ void or_diagnostics(const or_params* P, const double* u, const double* v, const 
     free(d);
 }
 
+/* Plane means at every height (Sec. 6: the x-y part of the paper's
+ * space-time averages), out[q (nz + 1) + k]:
+ *   q = 0 u, 1 v, 2 u^2, 3 v^2, 4 nu_T on the cell planes k < nz (0 at k = nz);
+ *   q = 5 w, 6 w^2 on the face planes k = 0..nz;
+ *   q = 7 u w on the x-z edges (i dx, k dz): u averaged over the cell planes
+ *   k - 1 and k (odd ghosts beyond the walls), w over the columns i - 1, i. */
+void or_plane_stats(const or_params* P, const double* u, const double* v, const double* w, const double* nut,
+                    double* out)
+{
+    const int nx = P->nx, ny = P->ny, nz = P->nz;
+    const double area = (double)nx * ny;
+    for (int k = 0; k <= nz; ++k) {
+        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                if (k < nz) {
+                    const double uc = u[ix(P, i, j, k)], vc = v[ix(P, i, j, k)];
+                    s[0] += uc;
+                    s[1] += vc;
+                    s[2] += uc * uc;
+                    s[3] += vc * vc;
+                    s[4] += nut[ix(P, i, j, k)];
+                }
+                const double wc = w[ix(P, i, j, k)];
+                s[5] += wc;
+                s[6] += wc * wc;
+                const double ue = 0.5 * (U(P, u, i, j, k - 1) + U(P, u, i, j, k));
+                const double we = 0.5 * (w[ix(P, i - 1, j, k)] + w[ix(P, i, j, k)]);
+                s[7] += ue * we;
+            }
+        for (int q = 0; q < 8; ++q) out[q * (nz + 1) + k] = s[q] / area;
+    }
+}
+
 /* ----------------------------------------------------------- time step -- */
 
 /* One time step of the projection scheme (Sec. 3.1), in the paper's order:

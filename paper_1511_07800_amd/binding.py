@@ -93,6 +93,8 @@ def load_library():
     L.stp_relax.restype = i32
     L.stp_residual_norm.argtypes = [vp, vp, vp, ctypes.POINTER(dbl)]
     L.stp_residual_norm.restype = i32
+    L.stp_plane_stats.argtypes = [vp, ctypes.POINTER(dbl)]
+    L.stp_plane_stats.restype = i32
     L.stp_residual_norm_noalloc.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, vp, vp, vp]
     L.stp_residual_norm_noalloc.restype = i32
     L.stp_lsq_guess.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, ctypes.POINTER(i32)]
@@ -235,6 +237,20 @@ class Channel:
         self.workspace[self._ws_off:self._ws_off + self._ws_bytes].copy_(ws)
         st = State(state["step"], state["nhist"], state.get("nproj", 0))
         self._check(self.lib.stp_set_state(self.handle, ctypes.byref(st)), "stp_set_state")
+
+    PLANE_STATS = ("u", "v", "uu", "vv", "nut", "w", "ww", "uw")
+
+    def plane_stats(self):
+        """stp_plane_stats: x-y means at every height, as a dict of numpy arrays
+        (u, v, uu, vv, nut on the nz cell planes; w, ww, uw on the nz + 1 face
+        planes)."""
+        import numpy as np
+        nz = self.nz
+        out = np.zeros(8 * (nz + 1))
+        self._check(self.lib.stp_plane_stats(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    "stp_plane_stats")
+        out = out.reshape(8, nz + 1)
+        return {name: (out[q, :nz].copy() if q < 5 else out[q].copy()) for q, name in enumerate(self.PLANE_STATS)}
 
     def schedule(self):
         m = ctypes.c_int32()

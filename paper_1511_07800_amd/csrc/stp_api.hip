@@ -1155,6 +1155,25 @@ stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape
     return STP_OK;
 }
 
+stp_status stp_plane_stats(stp_ctx* ctx, double* out)
+{
+    if (!ctx) return STP_EINVAL;
+    ctx->err.clear();
+    if (!out) {
+        ctx->err = "stp_plane_stats: NULL output";
+        return STP_EINVAL;
+    }
+    const size_t count = (size_t)kPlaneStats * (ctx->g.nz + 1);
+    if (count > (size_t)kMaxPartBlocks * 8) {
+        ctx->err = "stp_plane_stats: too many planes for the partials";
+        return STP_EINVAL;
+    }
+    CHK(plane_stats(ctx->g, ctx->u, ctx->v, ctx->w, ctx->nut, ctx->part, ctx->s));
+    CHK(hipMemcpyAsync(out, ctx->part, count * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+    CHK(hipStreamSynchronize(ctx->s));
+    return STP_OK;
+}
+
 stp_status stp_get_state(const stp_ctx* ctx, stp_state* out)
 {
     if (!ctx || !out) return STP_EINVAL;

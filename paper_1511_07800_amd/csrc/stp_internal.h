@@ -126,5 +126,10 @@ hipError_t half_scaled(_Float16* dst, const float* r, long long n, float scale, 
 hipError_t project(const Geo& g, const double* p, double* u, double* v, double* w, double dt, hipStream_t s);
 hipError_t diagnostics(const Geo& g, const double* u, const double* v, const double* w, double dt, double* part,
                        double* res, hipStream_t s);
+// Plane means at every height (kPlaneStats quantities, see k_plane_stats)
+// into out[q (nz + 1) + k], a device array of kPlaneStats (nz + 1) doubles.
+constexpr int kPlaneStats = 8;
+hipError_t plane_stats(const Geo& g, const double* u, const double* v, const double* w, const double* nut,
+                       double* out, hipStream_t s);
 
 }  // namespace stp

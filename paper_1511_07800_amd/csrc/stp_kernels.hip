@@ -912,6 +912,49 @@ __global__ __launch_bounds__(256) void k_diag(Geo g, int kchunk, const double* _
     if (threadIdx.x == 0 && threadIdx.y == 0) part[4 * nb + b] = r;
 }
 
+// ---- plane statistics (Sec. 6: averages over x and y at each height) -------
+
+// One workgroup per height k = 0..nz; sums over the plane in a fixed order,
+// written as plane means to out[q (nz+1) + k]:
+//   q = 0 u, 1 v, 2 u^2, 3 v^2, 4 nu_T on the cell planes k < nz (0 at k = nz);
+//   q = 5 w, 6 w^2 on the face planes k = 0..nz;
+//   q = 7 u w on the x-z edges (i dx, k dz): u averaged over the planes k-1
+//   and k (odd ghosts beyond the walls), w over the columns i-1 and i.
+__global__ __launch_bounds__(256) void k_plane_stats(Geo g, const double* __restrict__ u, const double* __restrict__ v,
+                                                     const double* __restrict__ w, const double* __restrict__ nut,
+                                                     double* __restrict__ out)
+{
+    __shared__ double lds[16];
+    const int k = blockIdx.x;
+    const long long pl = g.plane;
+    double acc[kPlaneStats] = {};
+    for (long long c = threadIdx.x; c < pl; c += blockDim.x) {
+        const int i = (int)(c % g.nx);
+        const long long cw = k * pl + c;  // face plane k
+        const long long iw = cw - i + wm(i, g.nx);
+        const double wc = w[cw];
+        acc[5] += wc;
+        acc[6] += wc * wc;
+        if (k < g.nz) {
+            const double uc = u[cw], vc = v[cw];
+            acc[0] += uc;
+            acc[1] += vc;
+            acc[2] += uc * uc;
+            acc[3] += vc * vc;
+            acc[4] += nut[cw];
+        }
+        const double ulo = k > 0 ? u[cw - pl] : -u[cw];
+        const double uhi = k < g.nz ? u[cw] : -u[cw - pl];
+        acc[7] += (0.5 * (ulo + uhi)) * (0.5 * (w[iw] + wc));
+    }
+    const double inv = 1.0 / (double)pl;
+#pragma unroll
+    for (int q = 0; q < kPlaneStats; ++q) {
+        const double r = block_reduce<false>(acc[q], lds);
+        if (threadIdx.x == 0) out[(long long)q * (g.nz + 1) + k] = r * inv;
+    }
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1156,6 +1199,13 @@ hipError_t project(const Geo& g, const double* p, double* u, double* v, double* 
 {
     const March m = march_shape(g, 2048);
     hipLaunchKernelGGL(k_project, m.grid, m.block, 0, s, g, m.kchunk, p, u, v, w, dt);
+    return hipGetLastError();
+}
+
+hipError_t plane_stats(const Geo& g, const double* u, const double* v, const double* w, const double* nut,
+                       double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_plane_stats, dim3(g.nz + 1), dim3(256), 0, s, g, u, v, w, nut, out);
     return hipGetLastError();
 }
 

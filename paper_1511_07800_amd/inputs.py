@@ -62,3 +62,52 @@ def faces_from_streamfunction(psi, dx, dz, ny):
     w[nz] = 0.0
     v = np.zeros_like(u)
     return np.ascontiguousarray(u), np.ascontiguousarray(v), np.ascontiguousarray(w)
+
+
+def les_curl_state(nx, ny, nz, lx, ly, lz, nu, dpdx, a=1.0 / 3.0, modes=5, pert_rms=None, seed=360):
+    """Turbulent-like start of the paper's LES (Sec. 6): u = a U0(z) +
+    s curl[f(z) A(x)], with U0 the discrete steady laminar profile,
+    f(z) = (1 - cos(2 pi z / lz)) / 2 (zero with zero slope at both walls) and
+    A_i = sum over kx, ky, kz = 1..modes of S_i sin(k.x) + C_i cos(k.x),
+    k = 2 pi (kx/lx, ky/ly, kz/lz), S and C uniform on [0, 1) (PCG64, seed).
+    The vector potential f A sits on the cell edges and the velocity is its
+    discrete curl on the faces, so the field is divergence-free to rounding
+    on the staggered grid and w vanishes on the walls.  The scale s brings
+    the rms of the curl term over all u, v, w faces to pert_rms (default: a
+    tenth of a U0 at the centreline).  Returns u, v, w."""
+    dx, dy, dz = lx / nx, ly / ny, lz / nz
+    r = rng(seed)
+    S = r.uniform(0.0, 1.0, size=(3, modes, modes, modes))
+    C = r.uniform(0.0, 1.0, size=(3, modes, modes, modes))
+    kk = np.arange(1, modes + 1)
+
+    def potential(comp, xs, ys, zs):
+        # A_comp(x, y, z) = Re sum (C - i S) e^{i k.x}, separably over kz, ky, kx
+        coef = C[comp] - 1j * S[comp]                                        # [kx, ky, kz]
+        ez = np.exp(1j * 2 * np.pi * np.outer(kk, zs) / lz)                  # [kz, z]
+        ey = np.exp(1j * 2 * np.pi * np.outer(kk, ys) / ly)                  # [ky, y]
+        ex = np.exp(1j * 2 * np.pi * np.outer(kk, xs) / lx)                  # [kx, x]
+        t = np.einsum("abc,cz->abz", coef, ez)
+        t = np.einsum("abz,by->ayz", t, ey)
+        a_ = np.einsum("ayz,ax->zyx", t, ex).real
+        f = 0.5 * (1.0 - np.cos(2 * np.pi * zs / lz))
+        return f[:, None, None] * a_
+
+    xc, yc = (np.arange(nx) + 0.5) * dx, (np.arange(ny) + 0.5) * dy
+    xf, yf = np.arange(nx) * dx, np.arange(ny) * dy
+    zf, zc = np.arange(nz + 1) * dz, (np.arange(nz) + 0.5) * dz
+    psx = potential(0, xc, yf, zf)   # x-edges ((i+1/2) dx, j dy, k dz): (nz+1, ny, nx)
+    psy = potential(1, xf, yc, zf)   # y-edges (i dx, (j+1/2) dy, k dz): (nz+1, ny, nx)
+    psz = potential(2, xf, yf, zc)   # z-edges (i dx, j dy, (k+1/2) dz): (nz, ny, nx)
+    u = (np.roll(psz, -1, axis=1) - psz) / dy - (psy[1:] - psy[:-1]) / dz
+    v = (psx[1:] - psx[:-1]) / dz - (np.roll(psz, -1, axis=2) - psz) / dx
+    w = (np.roll(psy, -1, axis=2) - psy) / dx - (np.roll(psx, -1, axis=1) - psx) / dy
+    w[0] = 0.0
+    w[nz] = 0.0
+    base = laminar_profile(nz, lz, nu, dpdx)
+    if pert_rms is None:
+        pert_rms = 0.1 * a * abs(dpdx) * lz * lz / (8.0 * nu)
+    rms = np.sqrt((np.sum(u * u) + np.sum(v * v) + np.sum(w * w)) / (u.size + v.size + w.size))
+    s = pert_rms / rms
+    u = a * base[:, None, None] + s * u
+    return np.ascontiguousarray(u), np.ascontiguousarray(s * v), np.ascontiguousarray(s * w)

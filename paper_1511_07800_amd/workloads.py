@@ -38,6 +38,13 @@ WORKLOADS = {
         les=1, cs=0.1, vd_a=25.0, steps=500, precision="mixed", poisson_rtol=1e-8, srj_reduction=1e-4,
         init="laminar_noise",
         noise=0.1, seed=7802),
+    # the paper's LES (Sec. 6 and its LES parameter table): height 1, friction
+    # velocity 1 (|G| = 2), Re_* = 360; the start is a U0 + curl[f A] with 5^3
+    # random Fourier modes (a = 1/3), statistics averaged over t in [20, 53]
+    "les_channel_paper_240x140x120": dict(
+        nx=240, ny=140, nz=120, lx=8.0, ly=4.0, lz=1.0, nu=1.0 / 360, dpdx=-2.0, dt=1e-4,
+        les=1, cs=0.1, vd_a=25.0, steps=530000, precision="mixed", poisson_rtol=1e-8, srj_reduction=1e-4,
+        init="curl_random_modes", curl_a=1.0 / 3.0, curl_modes=5, seed=360, t_stats=(20.0, 53.0)),
 }
 
 

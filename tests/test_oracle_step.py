@@ -346,3 +346,41 @@ def test_eddy_viscosity_field_and_max_closed_form():
     ref = P.nu + (0.1 * delta * phi) ** 2 * smag
     np.testing.assert_allclose(nut, np.broadcast_to(ref[:, None, None], nut.shape), rtol=1e-13)
     assert mx == pytest.approx(ref.max(), rel=1e-13)
+
+
+def test_plane_stats_closed_forms():
+    """or_plane_stats on fields with closed-form plane means (Sec. 6 averages):
+    u = U(z) + alpha sin(2 pi x/Lx) on the x-faces, v = beta cos(2 pi y/Ly),
+    w = gamma sin(2 pi x/Lx) on the interior z-faces, nu_T = c.  Over a full
+    period the sines average to 0 and their squares to 1/2, so <u> = U,
+    <u^2> = U^2 + alpha^2/2, <v> = 0, <v^2> = beta^2/2, <w> = 0,
+    <w^2> = gamma^2/2 inside and 0 on the walls, <nu_T> = c; on the x-z edges
+    u is (U_{k-1} + U_k)/2 + alpha sin(2 pi x_i/Lx) and w interpolated in x is
+    gamma cos(pi dx/Lx) sin(2 pi x_i/Lx), so <u w> = alpha gamma cos(pi dx/Lx)/2
+    inside and 0 on the walls (odd ghosts make u vanish there)."""
+    nx, ny, nz, lx, ly, lz = 12, 10, 9, 3.0, 2.0, 1.5
+    P = oracle.make_params(nx, ny, nz, lx, ly, lz)
+    al, be, ga, c = 0.7, -1.3, 0.4, 0.05
+    zc = (np.arange(nz) + 0.5) * lz / nz
+    U = 3.0 + np.sin(zc) * zc
+    xf = np.arange(nx) * lx / nx
+    xc = (np.arange(nx) + 0.5) * lx / nx
+    yf = np.arange(ny) * ly / ny
+    u = U[:, None, None] + al * np.sin(2 * np.pi * xf / lx)[None, None, :] + 0 * yf[None, :, None]
+    v = np.broadcast_to(be * np.cos(2 * np.pi * yf / ly)[None, :, None], (nz, ny, nx)).copy()
+    w = np.zeros((nz + 1, ny, nx))
+    w[1:nz] = ga * np.sin(2 * np.pi * xc / lx)[None, None, :]
+    nut = np.full((nz, ny, nx), c)
+    st = oracle.plane_stats(P, u, v, w, nut)
+    np.testing.assert_allclose(st["u"], U, rtol=1e-14)
+    np.testing.assert_allclose(st["uu"], U * U + al * al / 2, rtol=1e-14)
+    np.testing.assert_allclose(st["v"], 0.0, atol=1e-15)
+    np.testing.assert_allclose(st["vv"], be * be / 2, rtol=1e-14)
+    np.testing.assert_allclose(st["nut"], c, rtol=1e-14)
+    np.testing.assert_allclose(st["w"], 0.0, atol=1e-15)
+    ww = np.full(nz + 1, ga * ga / 2)
+    ww[0] = ww[nz] = 0.0
+    np.testing.assert_allclose(st["ww"], ww, rtol=1e-14, atol=1e-300)
+    uw = np.full(nz + 1, al * ga * np.cos(np.pi / nx) / 2)
+    uw[0] = uw[nz] = 0.0
+    np.testing.assert_allclose(st["uw"], uw, rtol=1e-13, atol=1e-16)
