@@ -75,7 +75,12 @@ typedef enum {
     STP_FP64 = 0,  /* every sweep and reduction in FP64 (the paper's method) */
     STP_MIXED = 1  /* FP32 relaxation sweeps inside an FP64 defect correction; each FP32 pass
                       solves for a power-of-two multiple of the residual that lies in FP32's
-                      normal range, so tiny and huge right-hand sides keep FP32 precision */
+                      normal range, so tiny and huge right-hand sides keep FP32 precision.
+                      The eddy viscosity, the explicit terms (FP32 Adams-Bashforth history) and
+                      the Crank-Nicolson increment run in FP32 on FP32 copies of the state (u
+                      as its departure from its FP64 x-y plane means); the state u, v, w, p,
+                      the Crank-Nicolson right-hand side, the residual and the correction stay
+                      FP64 */
 } stp_precision;
 
 typedef enum {
@@ -258,7 +263,9 @@ stp_status stp_lsq_guess(stp_ctx* ctx, int32_t k, const void* const* x_dev, cons
                          const void* b_dev, void* out_dev, int32_t* rank);
 
 /* Borrowed view of a field: device pointer, shape {nz or nz+1, ny, nx}
- * (slowest first) and dtype.  STP_W has nz+1 planes. */
+ * (slowest first) and dtype.  STP_W has nz+1 planes.  Every field is FP64,
+ * except STP_NUT in the mixed mode, which computes and keeps nu_T in FP32
+ * (STP_DTYPE_F32). */
 stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape[3], int32_t* dtype);
 
 /* Plane averages of the current state at every height, the x-y means from

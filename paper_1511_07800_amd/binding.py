@@ -212,14 +212,16 @@ class Channel:
         return rc
 
     def field(self, which):
-        """Borrowed torch view (float64) of a library field."""
+        """Borrowed torch view of a library field (float64; nu_T is float32 in
+        the mixed mode, as stp_fields reports)."""
         ptr = ctypes.c_void_p()
         shape = (ctypes.c_int64 * 3)()
         dt = ctypes.c_int32()
         self._check(self.lib.stp_fields(self.handle, which, ctypes.byref(ptr), shape, ctypes.byref(dt)), "stp_fields")
         n = shape[0] * shape[1] * shape[2]
         off = ptr.value - self.workspace.data_ptr()
-        return self.workspace[off:off + 8 * n].view(self.torch.float64).view(shape[0], shape[1], shape[2])
+        tdt, size = {STP_DTYPE_F64: (self.torch.float64, 8), STP_DTYPE_F32: (self.torch.float32, 4)}[dt.value]
+        return self.workspace[off:off + size * n].view(tdt).view(shape[0], shape[1], shape[2])
 
     def checkpoint(self):
         """(copy of the workspace, host state): everything stp_step advances."""

@@ -33,7 +33,10 @@ struct stp_ctx {
     double* hp[kMaxProj] = {};
     double* hb[kMaxProj] = {};
     int nproj = 0;
-    double* e[3][3] = {};   // Adams-Bashforth history, [slot][component]
+    double* e[3][3] = {};   // Adams-Bashforth history, [slot][component] (FP64 mode)
+    float* e32[3][3] = {};  // the same in FP32 (mixed mode)
+    float *u32 = nullptr, *v32 = nullptr, *w32 = nullptr;  // FP32 copies of the state (mixed mode stencils)
+    double* ub = nullptr;  // plane means of u; u32 holds u minus them (mixed mode)
     // FP32 work arrays of the mixed solve
     float *e0 = nullptr, *e1 = nullptr, *r32 = nullptr;
     _Float16* r16 = nullptr;  // mixed_rhs16: scaled FP16 copy of r32
@@ -140,8 +143,8 @@ const char* validate(const stp_config& c)
 
 // Byte offsets of every array in the workspace.
 struct Layout {
-    size_t u, v, w, p, ptmp, b, nut, rhs[3], tmp, p1, p2, hp[kMaxProj], hb[kMaxProj], e[3][3], e0, e1, r32, r16,
-        nut32, cnd, cna, cnb, part, res, total;
+    size_t u, v, w, p, ptmp, b, nut, rhs[3], tmp, p1, p2, hp[kMaxProj], hb[kMaxProj], e[3][3], e32[3][3], u32, v32,
+        w32, ub, e0, e1, r32, r16, nut32, cnd, cna, cnb, part, res, total;
 };
 
 Layout layout(const stp_config& c)
@@ -160,7 +163,8 @@ Layout layout(const stp_config& c)
     L.p = take(n * 8);
     L.ptmp = take(n * 8);
     L.b = take(n * 8);
-    L.nut = take(n * 8);
+    const bool mixed = c.precision == STP_MIXED;
+    if (!mixed) L.nut = take(n * 8);
     for (int q = 0; q < 3; ++q) L.rhs[q] = take((q == 2 ? nw : n) * 8);
     L.tmp = take(nw * 8);
     if (c.extrap_order >= 1) L.p1 = take(n * 8);
@@ -170,7 +174,16 @@ Layout layout(const stp_config& c)
         L.hb[j] = take(n * 8);
     }
     for (int sl = 0; sl < 3; ++sl)
-        for (int q = 0; q < 3; ++q) L.e[sl][q] = take((q == 2 ? nw : n) * 8);
+        for (int q = 0; q < 3; ++q) {
+            if (mixed) L.e32[sl][q] = take((q == 2 ? nw : n) * 4);
+            else L.e[sl][q] = take((q == 2 ? nw : n) * 8);
+        }
+    if (mixed) {
+        L.u32 = take(n * 4);
+        L.v32 = take(n * 4);
+        L.w32 = take(nw * 4);
+        L.ub = take((size_t)c.nz * 8);
+    }
     L.e0 = take(n * 4);
     L.e1 = take(n * 4);
     L.r32 = take(n * 4);
@@ -619,14 +632,27 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
     CHK(hipEventRecord(ctx->ev[0], s));
     CHK(zero_walls(g, ctx->w, s));
 
-    // 1. eddy viscosity at level n (Sec. 2.2)
+    // 1. eddy viscosity at level n (Sec. 2.2); the mixed mode runs this and
+    //    the explicit terms on FP32 copies of the FP64 state
+    const bool mixed = c.precision == STP_MIXED;
+    if (mixed) {
+        CHK(round_departure_f32(g, ctx->u32, ctx->u, ctx->ub, s));
+        CHK(round_to_f32(ctx->v32, ctx->v, g.n, s));
+        CHK(round_to_f32(ctx->w32, ctx->w, g.nw, s));
+    }
     double nut_max = c.nu;
     if (c.les) {
         const double delta = 2.0 * std::cbrt((c.lx / c.nx) * (c.ly / c.ny) * (c.lz / c.nz));
         const double utau = std::sqrt(0.5 * c.lz * std::fabs(c.dpdx));
         const double inv_wall_unit = utau / (c.nu * c.vd_a);
-        CHK(nut_smagorinsky(g, ctx->u, ctx->v, ctx->w, ctx->nut, c.nu, c.cs * delta, inv_wall_unit, c.lz, ctx->part,
-                            ctx->res, s));
+        if (mixed)
+            CHK(nut_smagorinsky<float>(g, ctx->u32, ctx->v32, ctx->w32, ctx->nut32, c.nu, c.cs * delta,
+                                       inv_wall_unit, c.lz, ctx->ub, ctx->part, ctx->res, s));
+        else
+            CHK(nut_smagorinsky<double>(g, ctx->u, ctx->v, ctx->w, ctx->nut, c.nu, c.cs * delta, inv_wall_unit, c.lz,
+                                        nullptr, ctx->part, ctx->res, s));
+    } else if (mixed) {
+        CHK(fill(ctx->nut32, (float)c.nu, g.n, s));
     } else {
         CHK(fill(ctx->nut, c.nu, g.n, s));
     }
@@ -639,13 +665,24 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
     if (n >= 2) { beta[0] = 23.0 / 12.0; beta[1] = -16.0 / 12.0; beta[2] = 5.0 / 12.0; }
     double* vel[3] = {ctx->u, ctx->v, ctx->w};
     for (int q = 0; q < 3; ++q) {
-        MomArgs a{};
-        a.u = ctx->u; a.v = ctx->v; a.w = ctx->w; a.nut = ctx->nut;
-        a.en = ctx->e[sl_n][q]; a.e1 = ctx->e[sl_1][q]; a.e2 = ctx->e[sl_2][q];
-        a.rhs = ctx->rhs[q];
-        a.beta0 = beta[0]; a.beta1 = beta[1]; a.beta2 = beta[2];
-        a.dt = c.dt; a.half_dt = 0.5 * c.dt; a.dpdx = c.dpdx; a.nu = c.nu;
-        CHK(momentum_rhs(g, q, a, s));
+        if (mixed) {
+            MomArgsT<float> a{};
+            a.u = ctx->u32; a.v = ctx->v32; a.w = ctx->w32; a.nut = ctx->nut32; a.ub = ctx->ub;
+            a.en = ctx->e32[sl_n][q]; a.e1 = ctx->e32[sl_1][q]; a.e2 = ctx->e32[sl_2][q];
+            a.rhs = ctx->rhs[q];
+            a.x64 = vel[q];
+            a.beta0 = beta[0]; a.beta1 = beta[1]; a.beta2 = beta[2];
+            a.dt = c.dt; a.half_dt = 0.5 * c.dt; a.dpdx = c.dpdx; a.nu = c.nu;
+            CHK(momentum_rhs<float>(g, q, a, s));
+        } else {
+            MomArgs a{};
+            a.u = ctx->u; a.v = ctx->v; a.w = ctx->w; a.nut = ctx->nut;
+            a.en = ctx->e[sl_n][q]; a.e1 = ctx->e[sl_1][q]; a.e2 = ctx->e[sl_2][q];
+            a.rhs = ctx->rhs[q];
+            a.beta0 = beta[0]; a.beta1 = beta[1]; a.beta2 = beta[2];
+            a.dt = c.dt; a.half_dt = 0.5 * c.dt; a.dpdx = c.dpdx; a.nu = c.nu;
+            CHK(momentum_rhs<double>(g, q, a, s));
+        }
     }
     if (c.les) {
         if ((rc = readback(ctx)) != STP_OK) return rc;
@@ -674,8 +711,6 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
         // delta to about 1e-7 of itself, so the target is max(cn_tol, 1e-7).
         int m32 = (int)std::ceil(std::log(std::max(c.cn_tol, kCnTol32)) / std::log(rho));
         m32 = std::max(2, std::min(m32, 999));
-        if (c.les) CHK(round_to_f32(ctx->nut32, ctx->nut, g.n, s));
-        else CHK(fill(ctx->nut32, (float)c.nu, g.n, s));
         for (int q = 0; q < 3; ++q) {
             float* a = ctx->cna;
             float* bb = ctx->cnb;
@@ -943,7 +978,8 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
     ctx->p = (double*)(base + L.p);
     ctx->ptmp = (double*)(base + L.ptmp);
     ctx->b = (double*)(base + L.b);
-    ctx->nut = (double*)(base + L.nut);
+    const bool mixed = c.precision == STP_MIXED;
+    if (!mixed) ctx->nut = (double*)(base + L.nut);
     for (int q = 0; q < 3; ++q) ctx->rhs[q] = (double*)(base + L.rhs[q]);
     ctx->tmp = (double*)(base + L.tmp);
     if (c.extrap_order >= 1) ctx->p1 = (double*)(base + L.p1);
@@ -953,7 +989,16 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
         ctx->hb[j] = (double*)(base + L.hb[j]);
     }
     for (int sl = 0; sl < 3; ++sl)
-        for (int q = 0; q < 3; ++q) ctx->e[sl][q] = (double*)(base + L.e[sl][q]);
+        for (int q = 0; q < 3; ++q) {
+            if (mixed) ctx->e32[sl][q] = (float*)(base + L.e32[sl][q]);
+            else ctx->e[sl][q] = (double*)(base + L.e[sl][q]);
+        }
+    if (mixed) {
+        ctx->u32 = (float*)(base + L.u32);
+        ctx->ub = (double*)(base + L.ub);
+        ctx->v32 = (float*)(base + L.v32);
+        ctx->w32 = (float*)(base + L.w32);
+    }
     ctx->e0 = (float*)(base + L.e0);
     ctx->e1 = (float*)(base + L.e1);
     ctx->r32 = (float*)(base + L.r32);
@@ -996,10 +1041,13 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
     if (e == hipSuccess) e = fill(ctx->w, 0.0, nw, ctx->s);
     if (e == hipSuccess) e = fill(ctx->rhs[2], 0.0, nw, ctx->s);
     if (e == hipSuccess) e = fill(ctx->tmp, 0.0, nw, ctx->s);
-    if (e == hipSuccess) e = fill(ctx->nut, c.nu, nn, ctx->s);
+    if (e == hipSuccess && ctx->nut) e = fill(ctx->nut, c.nu, nn, ctx->s);
+    if (e == hipSuccess && ctx->nut32) e = fill(ctx->nut32, (float)c.nu, nn, ctx->s);
     for (int sl = 0; sl < 3; ++sl)
-        for (int q = 0; q < 3; ++q)
-            if (e == hipSuccess) e = fill(ctx->e[sl][q], 0.0, q == 2 ? nw : nn, ctx->s);
+        for (int q = 0; q < 3; ++q) {
+            if (e == hipSuccess && ctx->e[sl][q]) e = fill(ctx->e[sl][q], 0.0, q == 2 ? nw : nn, ctx->s);
+            if (e == hipSuccess && ctx->e32[sl][q]) e = fill(ctx->e32[sl][q], 0.0f, q == 2 ? nw : nn, ctx->s);
+        }
     float* zero32[] = {ctx->e0, ctx->e1, ctx->r32};
     for (float* a : zero32) if (e == hipSuccess) e = fill(a, 0.0f, nn, ctx->s);
     if (e == hipSuccess) e = fill(ctx->res, 0.0, RES_COUNT, ctx->s);
@@ -1141,7 +1189,17 @@ stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape
     case STP_V: ptr = ctx->v; break;
     case STP_W: ptr = ctx->w; planes = ctx->g.nz + 1; break;
     case STP_P: ptr = ctx->p; break;
-    case STP_NUT: ptr = ctx->nut; break;
+    case STP_NUT:
+        if (ctx->cfg.precision == STP_MIXED) {  // the mixed mode keeps nu_T in FP32 only
+            *dev_ptr = ctx->nut32;
+            shape[0] = ctx->g.nz;
+            shape[1] = ctx->g.ny;
+            shape[2] = ctx->g.nx;
+            *dtype = STP_DTYPE_F32;
+            return STP_OK;
+        }
+        ptr = ctx->nut;
+        break;
     case STP_RHS: ptr = ctx->b; break;
     default:
         ctx->err = "stp_fields: unknown field";
@@ -1168,7 +1226,8 @@ stp_status stp_plane_stats(stp_ctx* ctx, double* out)
         ctx->err = "stp_plane_stats: too many planes for the partials";
         return STP_EINVAL;
     }
-    CHK(plane_stats(ctx->g, ctx->u, ctx->v, ctx->w, ctx->nut, ctx->part, ctx->s));
+    if (ctx->cfg.precision == STP_MIXED) CHK(plane_stats(ctx->g, ctx->u, ctx->v, ctx->w, ctx->nut32, ctx->part, ctx->s));
+    else CHK(plane_stats(ctx->g, ctx->u, ctx->v, ctx->w, ctx->nut, ctx->part, ctx->s));
     CHK(hipMemcpyAsync(out, ctx->part, count * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
     CHK(hipStreamSynchronize(ctx->s));
     return STP_OK;

@@ -69,21 +69,35 @@ hipError_t proj_combine(int k, const double* const* x, const double* a, double* 
 hipError_t sumsq_into(const double* a, long long n, double* part, double* res, int slot, hipStream_t s);
 hipError_t zero_walls(const Geo& g, double* w, hipStream_t s);
 
-hipError_t nut_smagorinsky(const Geo& g, const double* u, const double* v, const double* w, double* nut,
-                           double nu, double cs_delta, double inv_wall_unit, double lz, double* part,
-                           double* res, hipStream_t s);
+// nu_T from velocities stored as T (FP64, or FP32 copies in the mixed mode),
+// written as T; max nu_T into res[RES_NUT_MAX].  For T = float, u holds the
+// departure u - ub[k] from the FP64 plane profile ub (round_departure_f32);
+// ub is unused for T = double.
+template <typename T>
+hipError_t nut_smagorinsky(const Geo& g, const T* u, const T* v, const T* w, T* nut, double nu, double cs_delta,
+                           double inv_wall_unit, double lz, const double* ub, double* part, double* res,
+                           hipStream_t s);
 
-// Explicit terms E^n and the Crank-Nicolson right-hand side R for component c.
-struct MomArgs {
-    const double *u, *v, *w, *nut;
-    double* en;          // E^n out
-    const double* e1;    // E^{n-1}
-    const double* e2;    // E^{n-2}
-    double* rhs;         // R out
+// Explicit terms E^n and the Crank-Nicolson right-hand side R for component
+// c, with the stencils in T (velocities, nu_T and the Adams-Bashforth
+// history stored as T) and R in FP64: for T = float R = x64 + the FP32
+// increment, x64 the component's FP64 state, and u holds u - ub[k] (both
+// unused for T = double).
+template <typename T>
+struct MomArgsT {
+    const T *u, *v, *w, *nut;
+    const double* ub;  // plane profile of u (T = float)
+    T* en;          // E^n out
+    const T* e1;    // E^{n-1}
+    const T* e2;    // E^{n-2}
+    double* rhs;    // R out
+    const double* x64;
     double beta0, beta1, beta2;
     double dt, half_dt, dpdx, nu;
 };
-hipError_t momentum_rhs(const Geo& g, int comp, const MomArgs& a, hipStream_t s);
+using MomArgs = MomArgsT<double>;
+template <typename T>
+hipError_t momentum_rhs(const Geo& g, int comp, const MomArgsT<T>& a, hipStream_t s);
 
 // One Crank-Nicolson iteration x_out = x + (R - (I - h L) x) * inv_shift.
 hipError_t cn_iterate(const Geo& g, int comp, const double* nut, double nu, const double* rhs, const double* x,
@@ -94,6 +108,9 @@ hipError_t cn_defect(const Geo& g, int comp, int phase, const float* nut32, doub
                      const float* d0in, float* d0out, const float* x, float* xo, double* uo, double half_dt,
                      double inv_shift, hipStream_t s);
 hipError_t round_to_f32(float* dst, const double* src, long long n, hipStream_t s);
+// ub[k] = plane mean of the cell field src on plane k (nz doubles), then
+// dst = FP32(src - ub[k]): the FP32 copy of u the mixed-mode stencils read
+hipError_t round_departure_f32(const Geo& g, float* dst, const double* src, double* ub, hipStream_t s);
 
 hipError_t divergence_rhs(const Geo& g, const double* u, const double* v, const double* w, double* b,
                           double inv_dt, double* part, double* res, hipStream_t s);
@@ -129,7 +146,8 @@ hipError_t diagnostics(const Geo& g, const double* u, const double* v, const dou
 // Plane means at every height (kPlaneStats quantities, see k_plane_stats)
 // into out[q (nz + 1) + k], a device array of kPlaneStats (nz + 1) doubles.
 constexpr int kPlaneStats = 8;
-hipError_t plane_stats(const Geo& g, const double* u, const double* v, const double* w, const double* nut,
-                       double* out, hipStream_t s);
+template <typename TN>
+hipError_t plane_stats(const Geo& g, const double* u, const double* v, const double* w, const TN* nut, double* out,
+                       hipStream_t s);
 
 }  // namespace stp

@@ -25,6 +25,24 @@ __device__ __forceinline__ long long at(const Geo& g, int i, int j, int k)
     return (long long)i + (long long)g.nx * j + g.plane * k;
 }
 
+// Reference profile of u in the mixed mode.  The FP32 copy of u holds the
+// departure u - ub[k] from a per-plane reference (the plane mean), so the
+// copy rounds the departure only and differences of it are exact in the
+// mean; the stencils add the reference's own contribution from the FP64
+// profile.  The odd wall ghost of u continues the profile as -ub[0] below the
+// bottom plane and -ub[nz - 1] above the top one.
+struct URef {
+    const double* __restrict__ ub;
+    int nz;
+    __device__ double at(int k) const { return k < 0 ? -ub[0] : (k >= nz ? -ub[nz - 1] : ub[k]); }
+    __device__ float mean(int k) const { return (float)ub[k]; }
+    // ub(k + 1) - ub(k), and the mean on the z-edge between planes k and k + 1
+    __device__ float dz(int k) const { return (float)(at(k + 1) - at(k)); }
+    __device__ float edge(int k) const { return (float)(0.5 * (at(k) + at(k + 1))); }
+};
+template <typename T>
+constexpr bool kRefU = std::is_same<T, float>::value;
+
 // ---- fixed-order reductions -------------------------------------------------
 
 template <bool MAX>
@@ -291,80 +309,95 @@ __global__ void k_half_scaled(_Float16* __restrict__ d, const float* __restrict_
 // with z+ the distance to the nearer wall times u_tau/nu.  |S|^2 =
 // 2(S11^2 + S22^2 + S33^2) + 4(<S12^2> + <S13^2> + <S23^2>), <.> the mean over
 // the four edges around the centre; u, v odd and w zero at the walls.
-__global__ __launch_bounds__(256) void k_nut(Geo g, int kchunk, const double* __restrict__ u,
-                                             const double* __restrict__ v, const double* __restrict__ w,
-                                             double* __restrict__ nut, double nu, double cs_delta,
-                                             double inv_wall_unit, double lz, double* __restrict__ part)
+// T: the type the velocities and nu_T are stored and computed in (FP64, or
+// FP32 in the mixed mode); the maximum is reduced in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nut(Geo g, int kchunk, const T* __restrict__ u, const T* __restrict__ v,
+                                             const T* __restrict__ w, T* __restrict__ nut, double nu_d,
+                                             double cs_delta_d, double inv_wall_unit_d, double lz_d,
+                                             const double* __restrict__ ub, double* __restrict__ part)
 {
+    const URef R{ub, g.nz};  // FP32 only: u holds u - ub (see URef)
     __shared__ double lds[16];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     double vmax = -INFINITY;
+    const T idx = (T)g.idx, idy = (T)g.idy, idz = (T)g.idz;
+    const T nu = (T)nu_d, cs_delta = (T)cs_delta_d, inv_wall_unit = (T)inv_wall_unit_d, lz = (T)lz_d;
+    const T h = T(0.5), q = T(0.25);
     if (i < g.nx && j < g.ny) {
         const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
         const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
-        const double dz = 1.0 / g.idz;
+        const T dz = T(1.0) / idz;
         // u and v with the odd wall ghosts; w's wall planes hold 0
-        auto U = [&](int ii, int jj, int kk) -> double {
+        auto U = [&](int ii, int jj, int kk) -> T {
             if (kk < 0) return -u[at(g, ii, jj, 0)];
             if (kk >= g.nz) return -u[at(g, ii, jj, g.nz - 1)];
             return u[at(g, ii, jj, kk)];
         };
-        auto V = [&](int ii, int jj, int kk) -> double {
+        auto V = [&](int ii, int jj, int kk) -> T {
             if (kk < 0) return -v[at(g, ii, jj, 0)];
             if (kk >= g.nz) return -v[at(g, ii, jj, g.nz - 1)];
             return v[at(g, ii, jj, kk)];
         };
-        auto Wf = [&](int ii, int jj, int kk) -> double { return w[at(g, ii, jj, kk)]; };
+        auto Wf = [&](int ii, int jj, int kk) -> T { return w[at(g, ii, jj, kk)]; };
         const int is[2] = {i, ip}, ism[2] = {im, i};
         const int js[2] = {j, jp}, jsm[2] = {jm, j};
         // x-z edge (i + di, kk) on row j and y-z edge (j + di, kk) on column i
+        // d_z u across the edge above plane kk - 1 (the profile's part added
+        // for the FP32 departure)
+        auto duz = [&](int ii, int kk) -> T {
+            if constexpr (kRefU<T>) return (U(ii, j, kk) - U(ii, j, kk - 1)) + R.dz(kk - 1);
+            else return U(ii, j, kk) - U(ii, j, kk - 1);
+        };
         auto s13at = [&](int di, int kk) {
-            return 0.5 * ((U(is[di], j, kk) - U(is[di], j, kk - 1)) * g.idz + (Wf(is[di], j, kk) - Wf(ism[di], j, kk)) * g.idx);
+            return h * (duz(is[di], kk) * idz + (Wf(is[di], j, kk) - Wf(ism[di], j, kk)) * idx);
         };
         auto s23at = [&](int di, int kk) {
-            return 0.5 * ((V(i, js[di], kk) - V(i, js[di], kk - 1)) * g.idz + (Wf(i, js[di], kk) - Wf(i, jsm[di], kk)) * g.idy);
+            return h * ((V(i, js[di], kk) - V(i, js[di], kk - 1)) * idz + (Wf(i, js[di], kk) - Wf(i, jsm[di], kk)) * idy);
         };
         // Along the march the edges above plane k become the edges below
         // plane k + 1, and the column's values on plane k + 1 are those of the
         // next step: both stay in registers.
-        double s13lo[2] = {s13at(0, k0), s13at(1, k0)}, s23lo[2] = {s23at(0, k0), s23at(1, k0)};
-        double uc = U(i, j, k0), ue = U(ip, j, k0), vc = V(i, j, k0), vn = V(i, jp, k0), wc = Wf(i, j, k0);
+        T s13lo[2] = {s13at(0, k0), s13at(1, k0)}, s23lo[2] = {s23at(0, k0), s23at(1, k0)};
+        T uc = U(i, j, k0), ue = U(ip, j, k0), vc = V(i, j, k0), vn = V(i, jp, k0), wc = Wf(i, j, k0);
         for (int k = k0; k < k1; ++k) {
-            const double uS = U(i, jm, k), uSE = U(ip, jm, k), uN = U(i, jp, k), uNE = U(ip, jp, k);
-            const double vW = V(im, j, k), vE = V(ip, j, k), vNW = V(im, jp, k), vNE = V(ip, jp, k);
-            const double uc1 = U(i, j, k + 1), ue1 = U(ip, j, k + 1), vc1 = V(i, j, k + 1), vn1 = V(i, jp, k + 1);
-            const double wc1 = Wf(i, j, k + 1), we1 = Wf(ip, j, k + 1), ww1 = Wf(im, j, k + 1);
-            const double wn1 = Wf(i, jp, k + 1), ws1 = Wf(i, jm, k + 1);
-            const double s11 = (ue - uc) * g.idx;
-            const double s22 = (vn - vc) * g.idy;
-            const double s33 = (wc1 - wc) * g.idz;
-            const double s13hi[2] = {0.5 * ((uc1 - uc) * g.idz + (wc1 - ww1) * g.idx),
-                                     0.5 * ((ue1 - ue) * g.idz + (we1 - wc1) * g.idx)};
-            const double s23hi[2] = {0.5 * ((vc1 - vc) * g.idz + (wc1 - ws1) * g.idy),
-                                     0.5 * ((vn1 - vn) * g.idz + (wn1 - wc1) * g.idy)};
+            const T uS = U(i, jm, k), uSE = U(ip, jm, k), uN = U(i, jp, k), uNE = U(ip, jp, k);
+            const T vW = V(im, j, k), vE = V(ip, j, k), vNW = V(im, jp, k), vNE = V(ip, jp, k);
+            const T uc1 = U(i, j, k + 1), ue1 = U(ip, j, k + 1), vc1 = V(i, j, k + 1), vn1 = V(i, jp, k + 1);
+            const T wc1 = Wf(i, j, k + 1), we1 = Wf(ip, j, k + 1), ww1 = Wf(im, j, k + 1);
+            const T wn1 = Wf(i, jp, k + 1), ws1 = Wf(i, jm, k + 1);
+            const T s11 = (ue - uc) * idx;
+            const T s22 = (vn - vc) * idy;
+            const T s33 = (wc1 - wc) * idz;
+            T duc = uc1 - uc, due = ue1 - ue;
+            if constexpr (kRefU<T>) {
+                const T d = R.dz(k);
+                duc += d;
+                due += d;
+            }
+            const T s13hi[2] = {h * (duc * idz + (wc1 - ww1) * idx), h * (due * idz + (we1 - wc1) * idx)};
+            const T s23hi[2] = {h * ((vc1 - vc) * idz + (wc1 - ws1) * idy), h * ((vn1 - vn) * idz + (wn1 - wc1) * idy)};
             // x-y edges (i + di, j + dj) on plane k
-            const double s12[4] = {0.5 * ((uc - uS) * g.idy + (vc - vW) * g.idx),
-                                   0.5 * ((ue - uSE) * g.idy + (vE - vc) * g.idx),
-                                   0.5 * ((uN - uc) * g.idy + (vn - vNW) * g.idx),
-                                   0.5 * ((uNE - ue) * g.idy + (vNE - vn) * g.idx)};
-            double a12 = 0.0, a13 = 0.0, a23 = 0.0;
+            const T s12[4] = {h * ((uc - uS) * idy + (vc - vW) * idx), h * ((ue - uSE) * idy + (vE - vc) * idx),
+                              h * ((uN - uc) * idy + (vn - vNW) * idx), h * ((uNE - ue) * idy + (vNE - vn) * idx)};
+            T a12 = T(0), a13 = T(0), a23 = T(0);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int di = e & 1, dj = e >> 1;
-                const double s13 = dj ? s13hi[di] : s13lo[di];
-                const double s23 = dj ? s23hi[di] : s23lo[di];
-                a12 += 0.25 * s12[e] * s12[e];
-                a13 += 0.25 * s13 * s13;
-                a23 += 0.25 * s23 * s23;
+                const T s13 = dj ? s13hi[di] : s13lo[di];
+                const T s23 = dj ? s23hi[di] : s23lo[di];
+                a12 += q * s12[e] * s12[e];
+                a13 += q * s13 * s13;
+                a23 += q * s23 * s23;
             }
-            const double s2 = 2.0 * (s11 * s11 + s22 * s22 + s33 * s33) + 4.0 * (a12 + a13 + a23);
-            const double zc = (k + 0.5) * dz;
-            const double dwall = fmin(zc, lz - zc);
-            const double l = cs_delta * (1.0 - exp(-dwall * inv_wall_unit));
-            const double val = nu + l * l * sqrt(s2);
+            const T s2 = T(2.0) * (s11 * s11 + s22 * s22 + s33 * s33) + T(4.0) * (a12 + a13 + a23);
+            const T zc = ((T)k + h) * dz;
+            const T dwall = fmin(zc, lz - zc);
+            const T l = cs_delta * (T(1.0) - exp(-dwall * inv_wall_unit));
+            const T val = nu + l * l * sqrt(s2);
             nut[at(g, i, j, k)] = val;
-            vmax = fmax(vmax, val);
+            vmax = fmax(vmax, (double)val);
             s13lo[0] = s13hi[0];
             s13lo[1] = s13hi[1];
             s23lo[0] = s23hi[0];
@@ -440,60 +473,107 @@ __device__ __forceinline__ TC visc_apply(const Geo& g, const NuT<TN, TC>& N, con
     }
 }
 
+// The Crank-Nicolson right-hand side R = x + dt sum_m beta_m E^{n-m} +
+// (dt/2) L x at face c: in FP64 as one expression; with FP32 stencils the
+// increment is formed in FP32 and added to the FP64 state x64, so R keeps the
+// state's precision and only the increment carries FP32 rounding.
+template <typename T>
+__device__ __forceinline__ void store_mom(const MomArgsT<T>& a, long long c, T xc, T E, T Ldiff, T dt, T b0, T b1,
+                                          T b2, T hdt)
+{
+    a.en[c] = E;
+    if constexpr (std::is_same<T, double>::value) {
+        a.rhs[c] = xc + dt * (b0 * E + b1 * a.e1[c] + b2 * a.e2[c]) + hdt * Ldiff;
+    } else {
+        a.rhs[c] = a.x64[c] + (double)(dt * (b0 * E + b1 * a.e1[c] + b2 * a.e2[c]) + hdt * Ldiff);
+    }
+}
+
+// Coefficients of the momentum kernels, rounded once to the stencil type.
+template <typename T>
+struct MomConst {
+    T idx, idy, idz, idx2, idy2, idz2, dt, hdt, b0, b1, b2, dpdx, nu;
+    __device__ MomConst(const Geo& g, const MomArgsT<T>& a)
+        : idx((T)g.idx), idy((T)g.idy), idz((T)g.idz), idx2((T)g.idx2), idy2((T)g.idy2), idz2((T)g.idz2),
+          dt((T)a.dt), hdt((T)a.half_dt), b0((T)a.beta0), b1((T)a.beta1), b2((T)a.beta2), dpdx((T)a.dpdx),
+          nu((T)a.nu)
+    {
+    }
+};
+
 // x-momentum on x-faces: E_u = -d_j(u_j u) + d_j(nu_T d_x u_j) - G and
 // R_u = u + dt sum_m beta_m E_u^{n-m} + (dt/2) d_j(nu_T d_j u).
-__global__ __launch_bounds__(256) void k_mom_u(Geo g, int kchunk, MomArgs a)
+template <typename T>
+__global__ __launch_bounds__(256) void k_mom_u(Geo g, int kchunk, MomArgsT<T> a)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
-    const double* __restrict__ u = a.u;
-    const double* __restrict__ v = a.v;
-    const double* __restrict__ w = a.w;
+    const T* __restrict__ u = a.u;
+    const T* __restrict__ v = a.v;
+    const T* __restrict__ w = a.w;
+    const MomConst<T> K(g, a);
+    const URef R{a.ub, g.nz};  // FP32 only: u holds u - ub (see URef)
+    const T h = T(0.5), q = T(0.25);
     auto C = [&](int ii, int jj, int kk) { return a.nut[at(g, ii, jj, kk)]; };
     const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
     // Carried along the march (the values of plane k + 1 become those of
     // plane k): u at the face's column on k - 1 and k, w under the face's
     // x-z edge, nu_T at the two centres of the face, and the x-z edge
     // viscosity below the face.
-    double uc = u[at(g, i, j, k0)], uBraw = k0 > 0 ? u[at(g, i, j, k0 - 1)] : 0.0;
-    double wI = w[at(g, i, j, k0)], wIm = w[at(g, im, j, k0)];
-    double nC = C(i, j, k0), nWc = C(im, j, k0);
-    double nB = k0 > 0 ? 0.25 * (C(im, j, k0 - 1) + C(i, j, k0 - 1) + nWc + nC) : a.nu;
+    T uc = u[at(g, i, j, k0)], uBraw = k0 > 0 ? u[at(g, i, j, k0 - 1)] : T(0);
+    T wI = w[at(g, i, j, k0)], wIm = w[at(g, im, j, k0)];
+    T nC = C(i, j, k0), nWc = C(im, j, k0);
+    T nB = k0 > 0 ? q * (C(im, j, k0 - 1) + C(i, j, k0 - 1) + nWc + nC) : K.nu;
     for (int k = k0; k < k1; ++k) {
         const long long c = at(g, i, j, k);
         const bool up = k + 1 < g.nz;
-        const double uTraw = up ? u[c + g.plane] : 0.0;
-        const double uE = u[at(g, ip, j, k)], uW = u[at(g, im, j, k)];
-        const double uN = u[at(g, i, jp, k)], uS = u[at(g, i, jm, k)];
-        const double uT = up ? uTraw : -uc;
-        const double uB = k > 0 ? uBraw : -uc;
+        const T uTraw = up ? u[c + g.plane] : T(0);
+        const T uE = u[at(g, ip, j, k)], uW = u[at(g, im, j, k)];
+        const T uN = u[at(g, i, jp, k)], uS = u[at(g, i, jm, k)];
+        const T uT = up ? uTraw : -uc;
+        const T uB = k > 0 ? uBraw : -uc;
         // convection, divergence form
-        const double ue = 0.5 * (uc + uE), uw = 0.5 * (uW + uc);
-        const double cx = (ue * ue - uw * uw) * g.idx;
-        const double vImjp = v[at(g, im, jp, k)], vIjp = v[at(g, i, jp, k)];
-        const double vImj = v[at(g, im, j, k)], vIj = v[at(g, i, j, k)];
-        const double vn = 0.5 * (vImjp + vIjp);
-        const double vs = 0.5 * (vImj + vIj);
-        const double cy = (vn * 0.5 * (uc + uN) - vs * 0.5 * (uS + uc)) * g.idy;
-        const double wIm1 = w[at(g, im, j, k + 1)], wI1 = w[at(g, i, j, k + 1)];
-        const double wt = 0.5 * (wIm1 + wI1);
-        const double wb = 0.5 * (wIm + wI);
-        const double cz = (wt * 0.5 * (uc + uT) - wb * 0.5 * (uB + uc)) * g.idz;
+        const T ue = h * (uc + uE), uw = h * (uW + uc);
+        const T vImjp = v[at(g, im, jp, k)], vIjp = v[at(g, i, jp, k)];
+        const T vImj = v[at(g, im, j, k)], vIj = v[at(g, i, j, k)];
+        const T vn = h * (vImjp + vIjp);
+        const T vs = h * (vImj + vIj);
+        const T wIm1 = w[at(g, im, j, k + 1)], wI1 = w[at(g, i, j, k + 1)];
+        const T wt = h * (wIm1 + wI1);
+        const T wb = h * (wIm + wI);
+        T cx, cy, cz;
+        if constexpr (kRefU<T>) {
+            // u = ub + u': the profile is constant on the plane, so
+            // ue^2 - uw^2 = (ue' - uw')(2 ub + ue' + uw') and the y flux
+            // difference is ub (vn - vs) + its departure part
+            const T ub = R.mean(k);
+            cx = (ue - uw) * (T(2) * ub + ue + uw) * K.idx;
+            cy = (ub * (vn - vs) + (vn * h * (uc + uN) - vs * h * (uS + uc))) * K.idy;
+            cz = (wt * (R.edge(k) + h * (uc + uT)) - wb * (R.edge(k - 1) + h * (uB + uc))) * K.idz;
+        } else {
+            cx = (ue * ue - uw * uw) * K.idx;
+            cy = (vn * h * (uc + uN) - vs * h * (uS + uc)) * K.idy;
+            cz = (wt * h * (uc + uT) - wb * h * (uB + uc)) * K.idz;
+        }
         // viscous terms
-        const double nE = nC, nW = nWc;
-        const double nN = 0.25 * (nWc + nC + C(im, jp, k) + C(i, jp, k));
-        const double nS = 0.25 * (C(im, jm, k) + C(i, jm, k) + nWc + nC);
-        const double nCn = up ? C(i, j, k + 1) : 0.0, nWn = up ? C(im, j, k + 1) : 0.0;
-        const double nT = up ? 0.25 * (nWc + nC + nWn + nCn) : a.nu;
-        const double dxx = (nE * (uE - uc) - nW * (uc - uW)) * g.idx2;
-        const double vy = (nN * (vIjp - vImjp) - nS * (vIj - vImj)) * (g.idx * g.idy);
-        const double vz = (nT * (wI1 - wIm1) - nB * (wI - wIm)) * (g.idx * g.idz);
-        const double E = -(cx + cy + cz) + (dxx + vy + vz) - a.dpdx;
-        const double Ldiff = dxx + (nN * (uN - uc) - nS * (uc - uS)) * g.idy2 + (nT * (uT - uc) - nB * (uc - uB)) * g.idz2;
-        a.en[c] = E;
-        a.rhs[c] = uc + a.dt * (a.beta0 * E + a.beta1 * a.e1[c] + a.beta2 * a.e2[c]) + a.half_dt * Ldiff;
+        const T nE = nC, nW = nWc;
+        const T nN = q * (nWc + nC + C(im, jp, k) + C(i, jp, k));
+        const T nS = q * (C(im, jm, k) + C(i, jm, k) + nWc + nC);
+        const T nCn = up ? C(i, j, k + 1) : T(0), nWn = up ? C(im, j, k + 1) : T(0);
+        const T nT = up ? q * (nWc + nC + nWn + nCn) : K.nu;
+        const T dxx = (nE * (uE - uc) - nW * (uc - uW)) * K.idx2;
+        const T vy = (nN * (vIjp - vImjp) - nS * (vIj - vImj)) * (K.idx * K.idy);
+        const T vz = (nT * (wI1 - wIm1) - nB * (wI - wIm)) * (K.idx * K.idz);
+        const T E = -(cx + cy + cz) + (dxx + vy + vz) - K.dpdx;
+        T dut = uT - uc, dub = uc - uB;
+        if constexpr (kRefU<T>) {
+            dut += R.dz(k);
+            dub += R.dz(k - 1);
+        }
+        const T Ldiff = dxx + (nN * (uN - uc) - nS * (uc - uS)) * K.idy2 + (nT * dut - nB * dub) * K.idz2;
+        store_mom(a, c, uc, E, Ldiff, K.dt, K.b0, K.b1, K.b2, K.hdt);
         uBraw = uc;
         uc = uTraw;
         wI = wI1;
@@ -505,53 +585,58 @@ __global__ __launch_bounds__(256) void k_mom_u(Geo g, int kchunk, MomArgs a)
 }
 
 // y-momentum on y-faces: E_v = -d_j(u_j v) + d_j(nu_T d_y u_j).
-__global__ __launch_bounds__(256) void k_mom_v(Geo g, int kchunk, MomArgs a)
+template <typename T>
+__global__ __launch_bounds__(256) void k_mom_v(Geo g, int kchunk, MomArgsT<T> a)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
-    const double* __restrict__ u = a.u;
-    const double* __restrict__ v = a.v;
-    const double* __restrict__ w = a.w;
+    const T* __restrict__ u = a.u;
+    const T* __restrict__ v = a.v;
+    const T* __restrict__ w = a.w;
+    const MomConst<T> K(g, a);
+    const URef R{a.ub, g.nz};  // FP32 only: u holds u - ub (see URef)
+    const T h = T(0.5), q = T(0.25);
     auto C = [&](int ii, int jj, int kk) { return a.nut[at(g, ii, jj, kk)]; };
     const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
     // carried as in k_mom_u, with x and y exchanged
-    double vc = v[at(g, i, j, k0)], vBraw = k0 > 0 ? v[at(g, i, j, k0 - 1)] : 0.0;
-    double wJ = w[at(g, i, j, k0)], wJm = w[at(g, i, jm, k0)];
-    double nC = C(i, j, k0), nSc = C(i, jm, k0);
-    double nB = k0 > 0 ? 0.25 * (C(i, jm, k0 - 1) + C(i, j, k0 - 1) + nSc + nC) : a.nu;
+    T vc = v[at(g, i, j, k0)], vBraw = k0 > 0 ? v[at(g, i, j, k0 - 1)] : T(0);
+    T wJ = w[at(g, i, j, k0)], wJm = w[at(g, i, jm, k0)];
+    T nC = C(i, j, k0), nSc = C(i, jm, k0);
+    T nB = k0 > 0 ? q * (C(i, jm, k0 - 1) + C(i, j, k0 - 1) + nSc + nC) : K.nu;
     for (int k = k0; k < k1; ++k) {
         const long long c = at(g, i, j, k);
         const bool up = k + 1 < g.nz;
-        const double vTraw = up ? v[c + g.plane] : 0.0;
-        const double vE = v[at(g, ip, j, k)], vW = v[at(g, im, j, k)];
-        const double vN = v[at(g, i, jp, k)], vS = v[at(g, i, jm, k)];
-        const double vT = up ? vTraw : -vc;
-        const double vB = k > 0 ? vBraw : -vc;
-        const double uIpjm = u[at(g, ip, jm, k)], uIpj = u[at(g, ip, j, k)];
-        const double uIjm = u[at(g, i, jm, k)], uIj = u[at(g, i, j, k)];
-        const double ue = 0.5 * (uIpjm + uIpj);
-        const double uw = 0.5 * (uIjm + uIj);
-        const double cx = (ue * 0.5 * (vc + vE) - uw * 0.5 * (vW + vc)) * g.idx;
-        const double vn = 0.5 * (vc + vN), vs = 0.5 * (vS + vc);
-        const double cy = (vn * vn - vs * vs) * g.idy;
-        const double wJm1 = w[at(g, i, jm, k + 1)], wJ1 = w[at(g, i, j, k + 1)];
-        const double wt = 0.5 * (wJm1 + wJ1);
-        const double wb = 0.5 * (wJm + wJ);
-        const double cz = (wt * 0.5 * (vc + vT) - wb * 0.5 * (vB + vc)) * g.idz;
-        const double nE = 0.25 * (nSc + C(ip, jm, k) + nC + C(ip, j, k));
-        const double nW = 0.25 * (C(im, jm, k) + nSc + C(im, j, k) + nC);
-        const double nN = nC, nS = nSc;
-        const double nCn = up ? C(i, j, k + 1) : 0.0, nSn = up ? C(i, jm, k + 1) : 0.0;
-        const double nT = up ? 0.25 * (nSc + nC + nSn + nCn) : a.nu;
-        const double vx = (nE * (uIpj - uIpjm) - nW * (uIj - uIjm)) * (g.idx * g.idy);
-        const double dyy = (nN * (vN - vc) - nS * (vc - vS)) * g.idy2;
-        const double vz = (nT * (wJ1 - wJm1) - nB * (wJ - wJm)) * (g.idy * g.idz);
-        const double E = -(cx + cy + cz) + (vx + dyy + vz);
-        const double Ldiff = (nE * (vE - vc) - nW * (vc - vW)) * g.idx2 + dyy + (nT * (vT - vc) - nB * (vc - vB)) * g.idz2;
-        a.en[c] = E;
-        a.rhs[c] = vc + a.dt * (a.beta0 * E + a.beta1 * a.e1[c] + a.beta2 * a.e2[c]) + a.half_dt * Ldiff;
+        const T vTraw = up ? v[c + g.plane] : T(0);
+        const T vE = v[at(g, ip, j, k)], vW = v[at(g, im, j, k)];
+        const T vN = v[at(g, i, jp, k)], vS = v[at(g, i, jm, k)];
+        const T vT = up ? vTraw : -vc;
+        const T vB = k > 0 ? vBraw : -vc;
+        const T uIpjm = u[at(g, ip, jm, k)], uIpj = u[at(g, ip, j, k)];
+        const T uIjm = u[at(g, i, jm, k)], uIj = u[at(g, i, j, k)];
+        const T ue = h * (uIpjm + uIpj);
+        const T uw = h * (uIjm + uIj);
+        T cx;
+        if constexpr (kRefU<T>) cx = (R.mean(k) * (h * (vE - vW)) + (ue * h * (vc + vE) - uw * h * (vW + vc))) * K.idx;
+        else cx = (ue * h * (vc + vE) - uw * h * (vW + vc)) * K.idx;
+        const T vn = h * (vc + vN), vs = h * (vS + vc);
+        const T cy = (vn * vn - vs * vs) * K.idy;
+        const T wJm1 = w[at(g, i, jm, k + 1)], wJ1 = w[at(g, i, j, k + 1)];
+        const T wt = h * (wJm1 + wJ1);
+        const T wb = h * (wJm + wJ);
+        const T cz = (wt * h * (vc + vT) - wb * h * (vB + vc)) * K.idz;
+        const T nE = q * (nSc + C(ip, jm, k) + nC + C(ip, j, k));
+        const T nW = q * (C(im, jm, k) + nSc + C(im, j, k) + nC);
+        const T nN = nC, nS = nSc;
+        const T nCn = up ? C(i, j, k + 1) : T(0), nSn = up ? C(i, jm, k + 1) : T(0);
+        const T nT = up ? q * (nSc + nC + nSn + nCn) : K.nu;
+        const T vx = (nE * (uIpj - uIpjm) - nW * (uIj - uIjm)) * (K.idx * K.idy);
+        const T dyy = (nN * (vN - vc) - nS * (vc - vS)) * K.idy2;
+        const T vz = (nT * (wJ1 - wJm1) - nB * (wJ - wJm)) * (K.idy * K.idz);
+        const T E = -(cx + cy + cz) + (vx + dyy + vz);
+        const T Ldiff = (nE * (vE - vc) - nW * (vc - vW)) * K.idx2 + dyy + (nT * (vT - vc) - nB * (vc - vB)) * K.idz2;
+        store_mom(a, c, vc, E, Ldiff, K.dt, K.b0, K.b1, K.b2, K.hdt);
         vBraw = vc;
         vc = vTraw;
         wJ = wJ1;
@@ -564,20 +649,24 @@ __global__ __launch_bounds__(256) void k_mom_v(Geo g, int kchunk, MomArgs a)
 
 // z-momentum on interior z-faces: E_w = -d_j(u_j w) + d_j(nu_T d_z u_j);
 // wall planes get E = R = 0.
-__global__ __launch_bounds__(256) void k_mom_w(Geo g, int kchunk, MomArgs a)
+template <typename T>
+__global__ __launch_bounds__(256) void k_mom_w(Geo g, int kchunk, MomArgsT<T> a)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     const int im = wm(i, g.nx), ip = wp(i, g.nx), jm = wm(j, g.ny), jp = wp(j, g.ny);
-    const double* __restrict__ u = a.u;
-    const double* __restrict__ v = a.v;
-    const double* __restrict__ w = a.w;
+    const T* __restrict__ u = a.u;
+    const T* __restrict__ v = a.v;
+    const T* __restrict__ w = a.w;
+    const MomConst<T> K(g, a);
+    const URef R{a.ub, g.nz};  // FP32 only: u holds u - ub (see URef)
+    const T h = T(0.5), q = T(0.25);
     auto C = [&](int ii, int jj, int kk) { return a.nut[at(g, ii, jj, kk)]; };
     const int k0 = blockIdx.z * kchunk, k1 = min(g.nz + 1, k0 + kchunk);
     auto wall = [&](int k) {
         const long long c = at(g, i, j, k);
-        a.en[c] = 0.0;
+        a.en[c] = T(0);
         a.rhs[c] = 0.0;
     };
     int kb = k0;
@@ -589,37 +678,46 @@ __global__ __launch_bounds__(256) void k_mom_w(Geo g, int kchunk, MomArgs a)
     if (kb < ke) {
         // Carried along the march: w at the column on k - 1 and k; u, v and
         // nu_T on the plane of centres below the face (k - 1).
-        double wB = w[at(g, i, j, kb - 1)], wc = w[at(g, i, j, kb)];
-        double uIp0 = u[at(g, ip, j, kb - 1)], uI0 = u[at(g, i, j, kb - 1)];
-        double vJp0 = v[at(g, i, jp, kb - 1)], vJ0 = v[at(g, i, j, kb - 1)];
-        double pC = C(i, j, kb - 1), pE = C(ip, j, kb - 1), pW = C(im, j, kb - 1), pN = C(i, jp, kb - 1),
-               pS = C(i, jm, kb - 1);
+        T wB = w[at(g, i, j, kb - 1)], wc = w[at(g, i, j, kb)];
+        T uIp0 = u[at(g, ip, j, kb - 1)], uI0 = u[at(g, i, j, kb - 1)];
+        T vJp0 = v[at(g, i, jp, kb - 1)], vJ0 = v[at(g, i, j, kb - 1)];
+        T pC = C(i, j, kb - 1), pE = C(ip, j, kb - 1), pW = C(im, j, kb - 1), pN = C(i, jp, kb - 1),
+          pS = C(i, jm, kb - 1);
         for (int k = kb; k < ke; ++k) {
             const long long c = at(g, i, j, k);
-            const double wE = w[at(g, ip, j, k)], wW = w[at(g, im, j, k)];
-            const double wN = w[at(g, i, jp, k)], wS = w[at(g, i, jm, k)];
-            const double wT = w[c + g.plane];
-            const double uIp1 = u[at(g, ip, j, k)], uI1 = u[at(g, i, j, k)];
-            const double vJp1 = v[at(g, i, jp, k)], vJ1 = v[at(g, i, j, k)];
-            const double ue = 0.5 * (uIp0 + uIp1);
-            const double uw = 0.5 * (uI0 + uI1);
-            const double cx = (ue * 0.5 * (wc + wE) - uw * 0.5 * (wW + wc)) * g.idx;
-            const double vn = 0.5 * (vJp0 + vJp1);
-            const double vs = 0.5 * (vJ0 + vJ1);
-            const double cy = (vn * 0.5 * (wc + wN) - vs * 0.5 * (wS + wc)) * g.idy;
-            const double wt = 0.5 * (wc + wT), wb = 0.5 * (wB + wc);
-            const double cz = (wt * wt - wb * wb) * g.idz;
-            const double cC = C(i, j, k), cE = C(ip, j, k), cW = C(im, j, k), cN = C(i, jp, k), cS = C(i, jm, k);
-            const double nE = 0.25 * (pC + pE + cC + cE), nW = 0.25 * (pW + pC + cW + cC);
-            const double nN = 0.25 * (pC + pN + cC + cN), nS = 0.25 * (pS + pC + cS + cC);
-            const double nT = cC, nB = pC;
-            const double vx = (nE * (uIp1 - uIp0) - nW * (uI1 - uI0)) * (g.idx * g.idz);
-            const double vy = (nN * (vJp1 - vJp0) - nS * (vJ1 - vJ0)) * (g.idy * g.idz);
-            const double dzz = (nT * (wT - wc) - nB * (wc - wB)) * g.idz2;
-            const double E = -(cx + cy + cz) + (vx + vy + dzz);
-            const double Ldiff = (nE * (wE - wc) - nW * (wc - wW)) * g.idx2 + (nN * (wN - wc) - nS * (wc - wS)) * g.idy2 + dzz;
-            a.en[c] = E;
-            a.rhs[c] = wc + a.dt * (a.beta0 * E + a.beta1 * a.e1[c] + a.beta2 * a.e2[c]) + a.half_dt * Ldiff;
+            const T wE = w[at(g, ip, j, k)], wW = w[at(g, im, j, k)];
+            const T wN = w[at(g, i, jp, k)], wS = w[at(g, i, jm, k)];
+            const T wT = w[c + g.plane];
+            const T uIp1 = u[at(g, ip, j, k)], uI1 = u[at(g, i, j, k)];
+            const T vJp1 = v[at(g, i, jp, k)], vJ1 = v[at(g, i, j, k)];
+            const T ue = h * (uIp0 + uIp1);
+            const T uw = h * (uI0 + uI1);
+            T cx;
+            if constexpr (kRefU<T>)
+                cx = (R.edge(k - 1) * (h * (wE - wW)) + (ue * h * (wc + wE) - uw * h * (wW + wc))) * K.idx;
+            else
+                cx = (ue * h * (wc + wE) - uw * h * (wW + wc)) * K.idx;
+            const T vn = h * (vJp0 + vJp1);
+            const T vs = h * (vJ0 + vJ1);
+            const T cy = (vn * h * (wc + wN) - vs * h * (wS + wc)) * K.idy;
+            const T wt = h * (wc + wT), wb = h * (wB + wc);
+            const T cz = (wt * wt - wb * wb) * K.idz;
+            const T cC = C(i, j, k), cE = C(ip, j, k), cW = C(im, j, k), cN = C(i, jp, k), cS = C(i, jm, k);
+            const T nE = q * (pC + pE + cC + cE), nW = q * (pW + pC + cW + cC);
+            const T nN = q * (pC + pN + cC + cN), nS = q * (pS + pC + cS + cC);
+            const T nT = cC, nB = pC;
+            T duE = uIp1 - uIp0, duW = uI1 - uI0;
+            if constexpr (kRefU<T>) {
+                const T d = R.dz(k - 1);
+                duE += d;
+                duW += d;
+            }
+            const T vx = (nE * duE - nW * duW) * (K.idx * K.idz);
+            const T vy = (nN * (vJp1 - vJp0) - nS * (vJ1 - vJ0)) * (K.idy * K.idz);
+            const T dzz = (nT * (wT - wc) - nB * (wc - wB)) * K.idz2;
+            const T E = -(cx + cy + cz) + (vx + vy + dzz);
+            const T Ldiff = (nE * (wE - wc) - nW * (wc - wW)) * K.idx2 + (nN * (wN - wc) - nS * (wc - wS)) * K.idy2 + dzz;
+            store_mom(a, c, wc, E, Ldiff, K.dt, K.b0, K.b1, K.b2, K.hdt);
             wB = wc;
             wc = wT;
             uIp0 = uIp1;
@@ -791,6 +889,28 @@ __global__ void k_round32(float* __restrict__ d, const double* __restrict__ s, l
         d[q] = (float)s[q];
 }
 
+// ub[k] = mean of s over plane k (one workgroup per plane, fixed order)
+__global__ __launch_bounds__(256) void k_plane_mean(const double* __restrict__ s, long long plane,
+                                                    double* __restrict__ ub)
+{
+    __shared__ double lds[16];
+    const double* __restrict__ p = s + plane * blockIdx.x;
+    double acc = 0.0;
+    for (long long q = threadIdx.x; q < plane; q += blockDim.x) acc += p[q];
+    const double r = block_reduce<false>(acc, lds);
+    if (threadIdx.x == 0) ub[blockIdx.x] = r / (double)plane;
+}
+
+// d = FP32(s - ub[k]) on plane k = blockIdx.y
+__global__ void k_round32_sub(float* __restrict__ d, const double* __restrict__ s, const double* __restrict__ ub,
+                              long long plane)
+{
+    const long long o = plane * blockIdx.y;
+    const double m = ub[blockIdx.y];
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < plane; q += (long long)gridDim.x * blockDim.x)
+        d[o + q] = (float)(s[o + q] - m);
+}
+
 // ---- divergence, Poisson right-hand side (Sec. 3.1) -------------------------
 
 __global__ __launch_bounds__(256) void k_div(Geo g, int kchunk, const double* __restrict__ u,
@@ -920,8 +1040,9 @@ __global__ __launch_bounds__(256) void k_diag(Geo g, int kchunk, const double* _
 //   q = 5 w, 6 w^2 on the face planes k = 0..nz;
 //   q = 7 u w on the x-z edges (i dx, k dz): u averaged over the planes k-1
 //   and k (odd ghosts beyond the walls), w over the columns i-1 and i.
+template <typename TN>
 __global__ __launch_bounds__(256) void k_plane_stats(Geo g, const double* __restrict__ u, const double* __restrict__ v,
-                                                     const double* __restrict__ w, const double* __restrict__ nut,
+                                                     const double* __restrict__ w, const TN* __restrict__ nut,
                                                      double* __restrict__ out)
 {
     __shared__ double lds[16];
@@ -941,7 +1062,7 @@ __global__ __launch_bounds__(256) void k_plane_stats(Geo g, const double* __rest
             acc[1] += vc;
             acc[2] += uc * uc;
             acc[3] += vc * vc;
-            acc[4] += nut[cw];
+            acc[4] += (double)nut[cw];
         }
         const double ulo = k > 0 ? u[cw - pl] : -u[cw];
         const double uhi = k < g.nz ? u[cw] : -u[cw - pl];
@@ -1064,26 +1185,36 @@ hipError_t zero_walls(const Geo& g, double* w, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t nut_smagorinsky(const Geo& g, const double* u, const double* v, const double* w, double* nut, double nu,
-                           double cs_delta, double inv_wall_unit, double lz, double* part, double* res, hipStream_t s)
+template <typename T>
+hipError_t nut_smagorinsky(const Geo& g, const T* u, const T* v, const T* w, T* nut, double nu, double cs_delta,
+                           double inv_wall_unit, double lz, const double* ub, double* part, double* res,
+                           hipStream_t s)
 {
     const March m = march_shape(g, 2048);
-    hipLaunchKernelGGL(k_nut, m.grid, m.block, 0, s, g, m.kchunk, u, v, w, nut, nu, cs_delta, inv_wall_unit, lz, part);
+    hipLaunchKernelGGL(k_nut<T>, m.grid, m.block, 0, s, g, m.kchunk, u, v, w, nut, nu, cs_delta, inv_wall_unit, lz,
+                       ub, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize(part, m.nblocks(), 1, 1u, res, RES_NUT_MAX, s);
 }
+template hipError_t nut_smagorinsky<double>(const Geo&, const double*, const double*, const double*, double*, double,
+                                            double, double, double, const double*, double*, double*, hipStream_t);
+template hipError_t nut_smagorinsky<float>(const Geo&, const float*, const float*, const float*, float*, double,
+                                           double, double, double, const double*, double*, double*, hipStream_t);
 
-hipError_t momentum_rhs(const Geo& g, int comp, const MomArgs& a, hipStream_t s)
+template <typename T>
+hipError_t momentum_rhs(const Geo& g, int comp, const MomArgsT<T>& a, hipStream_t s)
 {
     Geo gw = g;
     if (comp == 2) gw.nz = g.nz + 1;  // march over all nz+1 z-face planes
     const March m = march_shape(gw, 2048);
-    if (comp == 0) hipLaunchKernelGGL(k_mom_u, m.grid, m.block, 0, s, g, m.kchunk, a);
-    else if (comp == 1) hipLaunchKernelGGL(k_mom_v, m.grid, m.block, 0, s, g, m.kchunk, a);
-    else hipLaunchKernelGGL(k_mom_w, m.grid, m.block, 0, s, g, m.kchunk, a);
+    if (comp == 0) hipLaunchKernelGGL(k_mom_u<T>, m.grid, m.block, 0, s, g, m.kchunk, a);
+    else if (comp == 1) hipLaunchKernelGGL(k_mom_v<T>, m.grid, m.block, 0, s, g, m.kchunk, a);
+    else hipLaunchKernelGGL(k_mom_w<T>, m.grid, m.block, 0, s, g, m.kchunk, a);
     return hipGetLastError();
 }
+template hipError_t momentum_rhs<double>(const Geo&, int, const MomArgsT<double>&, hipStream_t);
+template hipError_t momentum_rhs<float>(const Geo&, int, const MomArgsT<float>&, hipStream_t);
 
 hipError_t cn_iterate(const Geo& g, int comp, const double* nut, double nu, const double* rhs, const double* x,
                       double* xout, double half_dt, double inv_shift, hipStream_t s)
@@ -1121,6 +1252,16 @@ hipError_t cn_defect(const Geo& g, int comp, int phase, const float* nut32, doub
 hipError_t round_to_f32(float* dst, const double* src, long long n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_round32, dim3(grid1d(n)), dim3(kBlock1d), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t round_departure_f32(const Geo& g, float* dst, const double* src, double* ub, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_plane_mean, dim3(g.nz), dim3(256), 0, s, src, g.plane, ub);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int bx = (int)std::max<long long>(1, std::min<long long>((g.plane + kBlock1d - 1) / kBlock1d, 64));
+    hipLaunchKernelGGL(k_round32_sub, dim3(bx, g.nz), dim3(kBlock1d), 0, s, dst, src, ub, g.plane);
     return hipGetLastError();
 }
 
@@ -1202,12 +1343,17 @@ hipError_t project(const Geo& g, const double* p, double* u, double* v, double* 
     return hipGetLastError();
 }
 
-hipError_t plane_stats(const Geo& g, const double* u, const double* v, const double* w, const double* nut,
-                       double* out, hipStream_t s)
+template <typename TN>
+hipError_t plane_stats(const Geo& g, const double* u, const double* v, const double* w, const TN* nut, double* out,
+                       hipStream_t s)
 {
-    hipLaunchKernelGGL(k_plane_stats, dim3(g.nz + 1), dim3(256), 0, s, g, u, v, w, nut, out);
+    hipLaunchKernelGGL(k_plane_stats<TN>, dim3(g.nz + 1), dim3(256), 0, s, g, u, v, w, nut, out);
     return hipGetLastError();
 }
+template hipError_t plane_stats<double>(const Geo&, const double*, const double*, const double*, const double*,
+                                        double*, hipStream_t);
+template hipError_t plane_stats<float>(const Geo&, const double*, const double*, const double*, const float*,
+                                       double*, hipStream_t);
 
 hipError_t diagnostics(const Geo& g, const double* u, const double* v, const double* w, double dt, double* part,
                        double* res, hipStream_t s)

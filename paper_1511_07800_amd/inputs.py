@@ -111,3 +111,23 @@ def les_curl_state(nx, ny, nz, lx, ly, lz, nu, dpdx, a=1.0 / 3.0, modes=5, pert_
     s = pert_rms / rms
     u = a * base[:, None, None] + s * u
     return np.ascontiguousarray(u), np.ascontiguousarray(s * v), np.ascontiguousarray(s * w)
+
+
+def os_paper_seed(nx, ny, nz, lx, lz, nu, dpdx, alpha, eps=1e-4, c=2.0 ** -0.5, s=-(2.0 ** -0.5)):
+    """The perturbation that starts the paper's Orr-Sommerfeld validation run
+    (Sec. 4.2) on the discrete steady laminar profile: du = -A(x) f'(z),
+    dw = f(z) A'(x), with A = eps (C cos(alpha x) + S sin(alpha x)) and
+    f = 1/2 + 1/2 sin(2 pi z / lz - pi/2).  It is laid on the staggered grid as
+    the discrete curl of the streamfunction psi = f A on the x-z edges, so
+    du = -d psi/dz and dw = d psi/dx hold exactly in difference form and the
+    field is divergence-free to rounding.  Returns u, v, w."""
+    dx, dz = lx / nx, lz / nz
+    xe = np.arange(nx) * dx
+    ze = np.arange(nz + 1) * dz
+    f = 0.5 + 0.5 * np.sin(2 * np.pi * ze / lz - np.pi / 2)
+    f[0] = f[-1] = 0.0
+    a = eps * (c * np.cos(alpha * xe) + s * np.sin(alpha * xe))
+    # faces_from_streamfunction gives u = d psi/dz and w = -d psi/dx: pass -psi
+    du, dv, dw = faces_from_streamfunction(-(f[:, None] * a[None, :]), dx, dz, ny)
+    u = laminar_profile(nz, lz, nu, dpdx)[:, None, None] + du
+    return np.ascontiguousarray(u), dv, dw

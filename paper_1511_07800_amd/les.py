@@ -53,6 +53,8 @@ def main(argv=None):
     ap.add_argument("--save", default=None)
     ap.add_argument("--restart", default=None)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--max-seconds", type=float, default=None,
+                    help="stop stepping after this much wall time (then save and report)")
     args = ap.parse_args(argv)
 
     import torch
@@ -84,8 +86,13 @@ def main(argv=None):
           flush=True)
     wall0 = time.perf_counter()
     sweeps = 0
+    done = 0
     for n in range(1, args.steps + 1):
+        if args.max_seconds is not None and time.perf_counter() - wall0 > args.max_seconds:
+            print(f"les: wall-time limit after {n - 1} steps", flush=True)
+            break
         st = ch.step(1)
+        done = n
         sweeps += st["poisson"]["sweeps"]
         t = t0_sim + n * wl["dt"]
         if n % args.every == 0:
@@ -104,9 +111,9 @@ def main(argv=None):
                   f"samples {nacc} ms/step {1e3 * el / n:.2f}", flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    t_end = t0_sim + args.steps * wl["dt"]
-    out = {"workload": args.workload, "t_start": t0_sim, "t_end": t_end, "steps": args.steps,
-           "ms_per_step": 1e3 * wall / args.steps, "sweeps_per_step": sweeps / args.steps, "rtol": rtol,
+    t_end = t0_sim + done * wl["dt"]
+    out = {"workload": args.workload, "t_start": t0_sim, "t_end": t_end, "steps": done,
+           "ms_per_step": 1e3 * wall / max(done, 1), "sweeps_per_step": sweeps / max(done, 1), "rtol": rtol,
            "t1": t1, "samples": nacc,
            "paper": {"U_mean": 15.39, "Re_mean": 5542, "U_cl": 18.30, "U_max_over_U_mean": 1.19, "C_f": 8.44e-3,
                      "window": [20.0, 53.0]},

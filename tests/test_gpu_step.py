@@ -174,3 +174,28 @@ def test_bad_config_rejected(gpu):
         Channel(8, 8, 8, 1.0, 1.0, 1.0, nu=-0.1, dpdx=-1.0, dt=1e-3)
     with pytest.raises(StpError):
         Channel(8, 8, 8, 1.0, 1.0, 1.0, nu=0.1, dpdx=-1.0, dt=0.0)
+
+
+def test_mixed_mode_eddy_viscosity_in_fp32(gpu):
+    """The mixed mode computes nu_T from FP32 copies of the state and keeps it
+    in FP32 (stp_fields reports the FP32 array): after one step it equals the
+    oracle's FP64 nu_T of the starting state to FP32 precision of the strain
+    (1e-5 of the largest eddy-viscosity increment), and the step's maximum
+    agrees likewise."""
+    import torch
+    from paper_1511_07800_amd import STP_MIXED, STP_NUT
+    g = (48, 32, 24, 2 * math.pi, math.pi, 2.0)
+    nx, ny, nz, lx, ly, lz = g
+    u, v, w = inputs.channel_state(nx, ny, nz, lz, 1 / 180, -1.0, noise=0.1, seed=37)
+    ch, _ = make_pair(g, 1 / 180, -1.0, 2e-5, 1, 0.0, 1, u, v, w, precision=STP_MIXED)
+    st = ch.step(1)
+    nut = ch.field(STP_NUT)
+    assert nut.dtype == torch.float32
+    P = oracle.make_params(nx, ny, nz, lx, ly, lz, nu=1 / 180, dpdx=-1.0, dt=2e-5, les=1)
+    ref, mx = oracle.nut(P, u, v, w)
+    got = nut.cpu().numpy().astype(np.float64)
+    scale = np.abs(ref - 1 / 180).max()
+    err = np.abs(got - ref).max() / scale
+    print(f"mixed nu_T: max err {err:.2e} of the largest eddy viscosity {scale:.3e}", flush=True)
+    assert err <= 1e-5
+    assert st["nut_max"] == pytest.approx(mx, rel=1e-6)
