@@ -82,6 +82,9 @@ def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap
     return ch
 
 
+PHASES = ("ms_nut", "ms_momentum", "ms_divergence", "ms_guess", "ms_poisson", "ms_projection")
+
+
 def time_steps(ch, steps, warmup, label):
     """Time `steps` whole LES steps after `warmup`; also sums the in-step
     relaxation statistics (sweeps, kernel launches and their device time,
@@ -95,12 +98,15 @@ def time_steps(ch, steps, warmup, label):
               f"relres0 {st['poisson']['relres0']:.2e} cfl {st['cfl']:.3f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     acc = {"sweeps": 0, "launches": 0, "ms_relax": 0.0, "corrections": 0}
+    acc_phase = dict.fromkeys(PHASES, 0.0)
     per_step = []
     t0 = time.perf_counter()
     for i in range(steps):
         st = ch.step(1)
         for k in acc:
             acc[k] += st["poisson"][k]
+        for k in acc_phase:
+            acc_phase[k] += st[k]
         per_step.append({"sweeps": st["poisson"]["sweeps"], "relres0": float(f"{st['poisson']['relres0']:.3e}"),
                          "proj_rank": st["proj_rank"]})
         print(f"[{label}] step {i + 1}/{steps}: sweeps {st['poisson']['sweeps']} outer {st['poisson']['outer']} "
@@ -116,6 +122,7 @@ def time_steps(ch, steps, warmup, label):
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    acc["phases"] = acc_phase
     return dt, acc, st, per_step
 
 
@@ -363,6 +370,7 @@ def run_variant(wl, args, name, precision, opt):
     out = {"steps_per_s": round(args.steps / t, 4), "ms_per_step": round(1e3 * t / args.steps, 2),
            "sweeps_per_step": acc["sweeps"] / args.steps,
            "gcell_updates_per_s": round(acc["sweeps"] * n / t / 1e9, 2), "warmup": args.warmup,
+           "phase_ms_per_step": {k[3:]: round(v / args.steps, 2) for k, v in acc["phases"].items()},
            "per_step": per_step}
     if learned:
         out.update({"ms_net_last": round(st["ms_net"], 2), "relres_prev_last": st["relres_prev"],

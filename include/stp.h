@@ -183,6 +183,15 @@ typedef struct {
     double relres_proj;    /* ... and of the least-squares guess (0 when not formed) */
     int32_t proj_used;     /* 1 if the solve started from the least-squares guess (or its refinement) */
     int32_t proj_rank;     /* history columns the least-squares guess used (0 when not formed) */
+    /* Device time of the step's phases in the order of Sec. 3.1 (stream-ordered events; with
+       ms_poisson they add up to ms_total), ms.  The same phases are roctx ranges named
+       "stp_step: <phase>" for rocprofv3 --marker-trace; with STP_TRACE_SYNC=1 in the
+       environment at stp_init each range also waits for its phase's device work. */
+    double ms_nut;         /* eddy viscosity (and the mixed mode's FP32 copies of the state) */
+    double ms_momentum;    /* explicit terms, Crank-Nicolson right-hand sides and iterations */
+    double ms_divergence;  /* b = div u* / dt and its mean removal */
+    double ms_guess;       /* Poisson guess: extrapolation, least squares, network (ms_net) */
+    double ms_projection;  /* history update, u = u* - dt grad p, diagnostics */
 } stp_step_stats;
 
 /* Bytes of device workspace the configuration needs (0 if cfg is invalid). */

@@ -56,7 +56,9 @@ class StepStats(ctypes.Structure):
                 ("relres_prev", ctypes.c_double), ("relres_learned", ctypes.c_double),
                 ("learned_used", ctypes.c_int32), ("extrap_used", ctypes.c_int32), ("ms_net", ctypes.c_double),
                 ("relres_extrap", ctypes.c_double), ("relres_proj", ctypes.c_double),
-                ("proj_used", ctypes.c_int32), ("proj_rank", ctypes.c_int32)]
+                ("proj_used", ctypes.c_int32), ("proj_rank", ctypes.c_int32),
+                ("ms_nut", ctypes.c_double), ("ms_momentum", ctypes.c_double), ("ms_divergence", ctypes.c_double),
+                ("ms_guess", ctypes.c_double), ("ms_projection", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("poisson", "pad")}

@@ -6,9 +6,12 @@
 #include "stp_internal.h"
 #include "stp_net.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -51,7 +54,10 @@ struct stp_ctx {
     double D = 0.0;             // Jacobi diagonal 2/dx^2 + 2/dy^2 + 2/dz^2
     int step = 0;
     stp::NetModel* net = nullptr;
-    hipEvent_t ev[6] = {};  // step start, solve start/end, step end; sweep sequence start/end
+    // step start, solve start/end, step end; sweep sequence start/end; ends of
+    // the eddy-viscosity, momentum and divergence phases
+    hipEvent_t ev[9] = {};
+    bool trace_sync = false;  // STP_TRACE_SYNC=1: phase ranges end after their device work
     std::string err;
 };
 
@@ -622,6 +628,34 @@ stp_status lsq_guess(stp_ctx* ctx, int k, const double* const* xs, const double*
     return STP_OK;
 }
 
+// The phases of one step as roctx ranges (rocprofv3 --marker-trace), in the
+// order of Sec. 3.1: eddy viscosity, momentum (explicit terms and
+// Crank-Nicolson), divergence, Poisson guess, Poisson solve, projection.  A
+// range covers the host code of its phase; with trace_sync it also waits for
+// the phase's device work, so that the ranges tile the step's device time.
+class PhaseRanges {
+  public:
+    explicit PhaseRanges(const stp_ctx* ctx) : ctx_(ctx) {}
+    ~PhaseRanges() { close(); }
+    void next(const char* name)
+    {
+        close();
+        roctxRangePushA(name);
+        open_ = true;
+    }
+    void close()
+    {
+        if (!open_) return;
+        if (ctx_->trace_sync) (void)hipStreamSynchronize(ctx_->s);
+        roctxRangePop();
+        open_ = false;
+    }
+
+  private:
+    const stp_ctx* ctx_;
+    bool open_ = false;
+};
+
 stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
 {
     const stp_config& c = ctx->cfg;
@@ -629,6 +663,8 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
     hipStream_t s = ctx->s;
     stp_step_stats st{};
     stp_status rc;
+    PhaseRanges phase(ctx);
+    phase.next("stp_step: eddy viscosity");
     CHK(hipEventRecord(ctx->ev[0], s));
     CHK(zero_walls(g, ctx->w, s));
 
@@ -658,6 +694,8 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
     }
 
     // 2. explicit terms and Crank-Nicolson right-hand sides (Sec. 3.1)
+    CHK(hipEventRecord(ctx->ev[6], s));
+    phase.next("stp_step: momentum");
     const int n = ctx->step;
     const int sl_n = n % 3, sl_1 = (n + 2) % 3, sl_2 = (n + 1) % 3;
     double beta[3] = {1.0, 0.0, 0.0};
@@ -737,8 +775,12 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
     }
 
     // 4. b = div(u*)/dt, mean removed; ||b||^2 into RES_B2
+    CHK(hipEventRecord(ctx->ev[7], s));
+    phase.next("stp_step: divergence");
     CHK(divergence_rhs(g, ctx->u, ctx->v, ctx->w, ctx->b, 1.0 / c.dt, ctx->part, ctx->res, s));
     CHK(remove_mean(ctx->b, g.n, ctx->res + RES_SUM_B, RES_B2, ctx->part, ctx->res, s));
+    CHK(hipEventRecord(ctx->ev[8], s));
+    phase.next("stp_step: Poisson guess");
 
     // 5. SRJ pressure solve from the warm start (Sec. 3.4)
     if (c.warm_start == STP_WS_ZERO) CHK(fill(ctx->p, 0.0, g.n, s));
@@ -837,11 +879,13 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
         st.ms_net = msn;
     }
     CHK(hipEventRecord(ctx->ev[1], s));
+    phase.next("stp_step: Poisson solve");
     if ((rc = solve(ctx, ctx->b, ctx->p, c.poisson_rtol, c.poisson_maxit, &st.poisson)) != STP_OK) {
         ctx->nproj = 0;
         return rc;
     }
     CHK(hipEventRecord(ctx->ev[2], s));
+    phase.next("stp_step: projection");
     if (c.proj_depth > 0) {
         // only converged solutions enter the least-squares history
         if (st.poisson.status == STP_OK) {
@@ -861,6 +905,7 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
     CHK(diagnostics(g, ctx->u, ctx->v, ctx->w, c.dt, ctx->part, ctx->res, s));
     CHK(hipEventRecord(ctx->ev[3], s));
     if ((rc = readback(ctx)) != STP_OK) return rc;
+    phase.close();
     st.max_div = ctx->host[RES_DIAG + 0];
     st.u_bulk = ctx->host[RES_DIAG + 1] / (double)g.n;
     st.u_max = ctx->host[RES_DIAG + 2];
@@ -872,6 +917,13 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
     st.ms_total = ms;
     CHK(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
     st.ms_poisson = ms;
+    const int bound[7] = {0, 6, 7, 8, 1, 2, 3};  // events between the phases, in order
+    double* phase_ms[6] = {&st.ms_nut, &st.ms_momentum, &st.ms_divergence, &st.ms_guess, &st.ms_poisson,
+                           &st.ms_projection};
+    for (int q = 0; q < 6; ++q) {
+        CHK(hipEventElapsedTime(&ms, ctx->ev[bound[q]], ctx->ev[bound[q + 1]]));
+        *phase_ms[q] = ms;
+    }
     ++ctx->step;
     st.step = ctx->step;
     if (out) *out = st;
@@ -1028,11 +1080,15 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
         delete ctx;
         return STP_ENOMEM;
     }
-    for (int q = 0; q < 6; ++q)
+    for (int q = 0; q < 9; ++q)
         if (hipEventCreate(&ctx->ev[q]) != hipSuccess) {
             stp_destroy(ctx);
             return STP_EDEVICE;
         }
+    {
+        const char* sync = std::getenv("STP_TRACE_SYNC");
+        ctx->trace_sync = sync && sync[0] == '1';
+    }
     // state at rest, empty history
     hipError_t e = hipSuccess;
     const long long nn = g.n, nw = g.nw;
@@ -1358,7 +1414,7 @@ stp_status stp_net_train_step(stp_ctx* ctx, const void* b, const void* p_prev, c
 stp_status stp_destroy(stp_ctx* ctx)
 {
     if (!ctx) return STP_OK;
-    for (int q = 0; q < 6; ++q)
+    for (int q = 0; q < 9; ++q)
         if (ctx->ev[q]) (void)hipEventDestroy(ctx->ev[q]);
     if (ctx->host) (void)hipHostFree(ctx->host);
     delete ctx->net;

@@ -140,6 +140,28 @@ def test_bitwise_deterministic(gpu):
         np.testing.assert_array_equal(outs[0][k], outs[1][k])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_phase_times_add_up_to_the_step(gpu, precision):
+    """The per-phase device times (eddy viscosity, momentum, divergence,
+    Poisson guess, Poisson solve, projection) are consecutive event intervals:
+    each is non-negative and together they make up ms_total."""
+    from paper_1511_07800_amd import Channel
+    g = (64, 32, 24, 2.0, 1.2, 2.0)
+    nx, ny, nz, lx, ly, lz = g
+    u, v, w = inputs.channel_state(nx, ny, nz, lz, 1 / 180, -1.0, noise=0.1, seed=37)
+    ch = Channel(nx, ny, nz, lx, ly, lz, nu=1 / 180, dpdx=-1.0, dt=2e-5, les=1, precision=precision,
+                 poisson_rtol=1e-8, poisson_maxit=100, proj_depth=4)
+    load_state(ch, u, v, w)
+    names = ("ms_nut", "ms_momentum", "ms_divergence", "ms_guess", "ms_poisson", "ms_projection")
+    for _ in range(4):
+        st = ch.step(1)
+        parts = [st[k] for k in names]
+        print(" ".join(f"{k} {st[k]:.3f}" for k in names), f"total {st['ms_total']:.3f}", flush=True)
+        assert min(parts) >= 0.0 and st["ms_poisson"] > 0.0 and st["ms_momentum"] > 0.0
+        assert sum(parts) == pytest.approx(st["ms_total"], rel=1e-4, abs=0.02)
+    ch.close()
+
+
 def test_warm_start_zero_same_solution(gpu):
     g = (40, 24, 20, 2.0, 1.2, 2.0)
     nx, ny, nz, lx, ly, lz = g
