@@ -65,14 +65,14 @@ def parse():
 
 
 def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap_order=0, proj_depth=0,
-                 rhs16=0):
+                 rhs16=0, stencils32=0):
     import torch
     from paper_1511_07800_amd import Channel, inputs
     ch = Channel(wl["nx"], wl["ny"], wl["nz"], wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"],
                  dt=wl["dt"], les=wl["les"], cs=wl.get("cs", 0.1), vd_a=wl.get("vd_a", 25.0), precision=precision,
                  poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=0 if FIXED_CYCLES else 1,
                  srj_reduction=wl.get("srj_reduction", 1e-3), learned_correction=learned_correction,
-                 extrap_order=extrap_order, proj_depth=proj_depth, mixed_rhs16=rhs16)
+                 extrap_order=extrap_order, proj_depth=proj_depth, mixed_rhs16=rhs16, stencils32=stencils32)
     u, v, w = inputs.channel_state(wl["nx"], wl["ny"], wl["nz"], wl["lz"], wl["nu"], wl["dpdx"],
                                    noise=wl.get("noise", 0.0), seed=wl.get("seed", 0))
     for k, a in enumerate((u, v, w)):
@@ -339,11 +339,16 @@ VARIANTS = [
     ("lsq_mixed", "mixed", {"proj_depth": PROJ_DEPTH}),
     ("learned_mixed", "mixed", {"learned": True}),
     ("learned_lsq_mixed_rhs16", "mixed", {"learned": True, "proj_depth": PROJ_DEPTH, "rhs16": 1}),
+    # the same with the eddy viscosity and explicit terms in FP32 (stencils32)
+    ("learned_lsq_mixed_rhs16_stencils32", "mixed",
+     {"learned": True, "proj_depth": PROJ_DEPTH, "rhs16": 1, "stencils32": 1}),
     ("fp64", "fp64", {}),
 ]
 EXTRA_VARIANTS = [
     ("extrap_mixed", "mixed", {"extrap_order": 2}),
     ("mixed_rhs16", "mixed", {"rhs16": 1}),
+    ("mixed_stencils32", "mixed", {"stencils32": 1}),
+    ("lsq_mixed_stencils32", "mixed", {"proj_depth": PROJ_DEPTH, "stencils32": 1}),
     ("lsq_mixed_rhs16", "mixed", {"proj_depth": PROJ_DEPTH, "rhs16": 1}),
     ("learned_lsq_mixed", "mixed", {"learned": True, "proj_depth": PROJ_DEPTH}),
     ("learned_mixed_correction", "mixed", {"learned": True, "correction": 1}),
@@ -359,7 +364,8 @@ def run_variant(wl, args, name, precision, opt):
     ch = make_channel(wl, STP_MIXED if precision == "mixed" else STP_FP64, args.rtol,
                       warm_start=STP_WS_LEARNED if learned else STP_WS_PREV,
                       learned_correction=opt.get("correction", 0), extrap_order=opt.get("extrap_order", 0),
-                      proj_depth=opt.get("proj_depth", 0), rhs16=opt.get("rhs16", 0))
+                      proj_depth=opt.get("proj_depth", 0), rhs16=opt.get("rhs16", 0),
+                      stencils32=opt.get("stencils32", 0))
     weights = None
     if learned:
         ch.net_init(training=False)

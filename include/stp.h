@@ -76,11 +76,10 @@ typedef enum {
     STP_MIXED = 1  /* FP32 relaxation sweeps inside an FP64 defect correction; each FP32 pass
                       solves for a power-of-two multiple of the residual that lies in FP32's
                       normal range, so tiny and huge right-hand sides keep FP32 precision.
-                      The eddy viscosity, the explicit terms (FP32 Adams-Bashforth history) and
-                      the Crank-Nicolson increment run in FP32 on FP32 copies of the state (u
-                      as its departure from its FP64 x-y plane means); the state u, v, w, p,
-                      the Crank-Nicolson right-hand side, the residual and the correction stay
-                      FP64 */
+                      The Crank-Nicolson increment runs in FP32 (defect form), and with
+                      stencils32 = 1 also the eddy viscosity and the explicit terms; the state
+                      u, v, w, p, the Crank-Nicolson right-hand side, the residual and the
+                      correction stay FP64 */
 } stp_precision;
 
 typedef enum {
@@ -146,6 +145,16 @@ typedef struct {
                                   the residual by at most about 1e-3 (FP16 rounds each element to
                                   within 4.9e-4), so the per-pass floor becomes max(srj_reduction,
                                   1e-3).  Adds nx*ny*nz halves to the workspace.  0: FP32. */
+    int32_t stencils32;        /* STP_MIXED only: 1 runs the eddy viscosity and the explicit momentum terms
+                                  in FP32 on FP32 copies of the state made each step (u as its departure
+                                  from its FP64 x-y plane means, so the copy rounds the departure only),
+                                  with nu_T and the Adams-Bashforth history stored in FP32, and forms the
+                                  Crank-Nicolson right-hand side as the FP64 state plus the FP32
+                                  increment.  The FP32 rounding of those terms enters each step's
+                                  Poisson right-hand side as noise the least-squares and learned guesses
+                                  cannot predict, which bounds their residual from below (about 3e-6 of
+                                  ||b|| on the 512x256x192 LES against 4e-7 with FP64 stencils) and costs
+                                  more sweeps than the stencils save there.  0: FP64 stencils. */
     void* stream;              /* hipStream_t for all work */
 } stp_config;
 

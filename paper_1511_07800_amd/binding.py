@@ -31,7 +31,8 @@ class Config(ctypes.Structure):
                 ("srj_reduction", ctypes.c_double), ("mixed_inner", ctypes.c_int32),
                 ("srj_adaptive", ctypes.c_int32), ("tblock", ctypes.c_int32),
                 ("cn_tol", ctypes.c_double), ("learned_correction", ctypes.c_int32), ("extrap_order", ctypes.c_int32),
-                ("proj_depth", ctypes.c_int32), ("mixed_rhs16", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("proj_depth", ctypes.c_int32), ("mixed_rhs16", ctypes.c_int32), ("stencils32", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class SolveStats(ctypes.Structure):
@@ -161,7 +162,7 @@ class Channel:
     def __init__(self, nx, ny, nz, lx, ly, lz, nu, dpdx, dt, les=0, cs=0.1, vd_a=25.0,
                  precision=STP_FP64, warm_start=STP_WS_PREV, poisson_rtol=1e-10, poisson_maxit=1000,
                  omega=None, srj_reduction=1e-3, mixed_inner=1, tblock=4, cn_tol=1e-13, srj_adaptive=0,
-                 learned_correction=0, extrap_order=0, proj_depth=0, mixed_rhs16=0,
+                 learned_correction=0, extrap_order=0, proj_depth=0, mixed_rhs16=0, stencils32=0,
                  device=None):
         import torch
         self.torch = torch
@@ -188,6 +189,7 @@ class Channel:
         cfg.extrap_order = int(extrap_order)
         cfg.proj_depth = int(proj_depth)
         cfg.mixed_rhs16 = int(mixed_rhs16)
+        cfg.stencils32 = int(stencils32)
         cfg.srj_adaptive = srj_adaptive
         cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self.cfg = cfg

@@ -144,6 +144,8 @@ const char* validate(const stp_config& c)
     if (c.proj_depth > 0 && c.warm_start == STP_WS_ZERO) return "proj_depth needs STP_WS_PREV or STP_WS_LEARNED";
     if (c.mixed_rhs16 != 0 && c.mixed_rhs16 != 1) return "mixed_rhs16 must be 0 or 1";
     if (c.mixed_rhs16 && c.precision != STP_MIXED) return "mixed_rhs16 needs STP_MIXED";
+    if (c.stencils32 != 0 && c.stencils32 != 1) return "stencils32 must be 0 or 1";
+    if (c.stencils32 && c.precision != STP_MIXED) return "stencils32 needs STP_MIXED";
     return nullptr;
 }
 
@@ -169,8 +171,9 @@ Layout layout(const stp_config& c)
     L.p = take(n * 8);
     L.ptmp = take(n * 8);
     L.b = take(n * 8);
-    const bool mixed = c.precision == STP_MIXED;
-    if (!mixed) L.nut = take(n * 8);
+    // FP32 eddy viscosity, explicit terms and history (stencils32)
+    const bool st32 = c.precision == STP_MIXED && c.stencils32;
+    if (!st32) L.nut = take(n * 8);
     for (int q = 0; q < 3; ++q) L.rhs[q] = take((q == 2 ? nw : n) * 8);
     L.tmp = take(nw * 8);
     if (c.extrap_order >= 1) L.p1 = take(n * 8);
@@ -181,10 +184,10 @@ Layout layout(const stp_config& c)
     }
     for (int sl = 0; sl < 3; ++sl)
         for (int q = 0; q < 3; ++q) {
-            if (mixed) L.e32[sl][q] = take((q == 2 ? nw : n) * 4);
+            if (st32) L.e32[sl][q] = take((q == 2 ? nw : n) * 4);
             else L.e[sl][q] = take((q == 2 ? nw : n) * 8);
         }
-    if (mixed) {
+    if (st32) {
         L.u32 = take(n * 4);
         L.v32 = take(n * 4);
         L.w32 = take(nw * 4);
@@ -668,10 +671,11 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
     CHK(hipEventRecord(ctx->ev[0], s));
     CHK(zero_walls(g, ctx->w, s));
 
-    // 1. eddy viscosity at level n (Sec. 2.2); the mixed mode runs this and
-    //    the explicit terms on FP32 copies of the FP64 state
+    // 1. eddy viscosity at level n (Sec. 2.2); with stencils32 this and the
+    //    explicit terms run on FP32 copies of the FP64 state
     const bool mixed = c.precision == STP_MIXED;
-    if (mixed) {
+    const bool st32 = mixed && c.stencils32;
+    if (st32) {
         CHK(round_departure_f32(g, ctx->u32, ctx->u, ctx->ub, s));
         CHK(round_to_f32(ctx->v32, ctx->v, g.n, s));
         CHK(round_to_f32(ctx->w32, ctx->w, g.nw, s));
@@ -681,17 +685,19 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
         const double delta = 2.0 * std::cbrt((c.lx / c.nx) * (c.ly / c.ny) * (c.lz / c.nz));
         const double utau = std::sqrt(0.5 * c.lz * std::fabs(c.dpdx));
         const double inv_wall_unit = utau / (c.nu * c.vd_a);
-        if (mixed)
+        if (st32)
             CHK(nut_smagorinsky<float>(g, ctx->u32, ctx->v32, ctx->w32, ctx->nut32, c.nu, c.cs * delta,
                                        inv_wall_unit, c.lz, ctx->ub, ctx->part, ctx->res, s));
         else
             CHK(nut_smagorinsky<double>(g, ctx->u, ctx->v, ctx->w, ctx->nut, c.nu, c.cs * delta, inv_wall_unit, c.lz,
                                         nullptr, ctx->part, ctx->res, s));
-    } else if (mixed) {
+    } else if (st32) {
         CHK(fill(ctx->nut32, (float)c.nu, g.n, s));
     } else {
         CHK(fill(ctx->nut, c.nu, g.n, s));
     }
+    // the mixed mode's Crank-Nicolson iterations read nu_T in FP32
+    if (mixed && !st32) CHK(round_to_f32(ctx->nut32, ctx->nut, g.n, s));
 
     // 2. explicit terms and Crank-Nicolson right-hand sides (Sec. 3.1)
     CHK(hipEventRecord(ctx->ev[6], s));
@@ -703,7 +709,7 @@ stp_status one_step(stp_ctx* ctx, stp_step_stats* out)
     if (n >= 2) { beta[0] = 23.0 / 12.0; beta[1] = -16.0 / 12.0; beta[2] = 5.0 / 12.0; }
     double* vel[3] = {ctx->u, ctx->v, ctx->w};
     for (int q = 0; q < 3; ++q) {
-        if (mixed) {
+        if (st32) {
             MomArgsT<float> a{};
             a.u = ctx->u32; a.v = ctx->v32; a.w = ctx->w32; a.nut = ctx->nut32; a.ub = ctx->ub;
             a.en = ctx->e32[sl_n][q]; a.e1 = ctx->e32[sl_1][q]; a.e2 = ctx->e32[sl_2][q];
@@ -1030,8 +1036,8 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
     ctx->p = (double*)(base + L.p);
     ctx->ptmp = (double*)(base + L.ptmp);
     ctx->b = (double*)(base + L.b);
-    const bool mixed = c.precision == STP_MIXED;
-    if (!mixed) ctx->nut = (double*)(base + L.nut);
+    const bool st32 = c.precision == STP_MIXED && c.stencils32;
+    if (!st32) ctx->nut = (double*)(base + L.nut);
     for (int q = 0; q < 3; ++q) ctx->rhs[q] = (double*)(base + L.rhs[q]);
     ctx->tmp = (double*)(base + L.tmp);
     if (c.extrap_order >= 1) ctx->p1 = (double*)(base + L.p1);
@@ -1042,10 +1048,10 @@ stp_status stp_init(const stp_config* cfg, void* ws, size_t bytes, stp_ctx** out
     }
     for (int sl = 0; sl < 3; ++sl)
         for (int q = 0; q < 3; ++q) {
-            if (mixed) ctx->e32[sl][q] = (float*)(base + L.e32[sl][q]);
+            if (st32) ctx->e32[sl][q] = (float*)(base + L.e32[sl][q]);
             else ctx->e[sl][q] = (double*)(base + L.e[sl][q]);
         }
-    if (mixed) {
+    if (st32) {
         ctx->u32 = (float*)(base + L.u32);
         ctx->ub = (double*)(base + L.ub);
         ctx->v32 = (float*)(base + L.v32);
@@ -1246,7 +1252,7 @@ stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape
     case STP_W: ptr = ctx->w; planes = ctx->g.nz + 1; break;
     case STP_P: ptr = ctx->p; break;
     case STP_NUT:
-        if (ctx->cfg.precision == STP_MIXED) {  // the mixed mode keeps nu_T in FP32 only
+        if (!ctx->nut) {  // stencils32 keeps nu_T in FP32 only
             *dev_ptr = ctx->nut32;
             shape[0] = ctx->g.nz;
             shape[1] = ctx->g.ny;
@@ -1282,7 +1288,7 @@ stp_status stp_plane_stats(stp_ctx* ctx, double* out)
         ctx->err = "stp_plane_stats: too many planes for the partials";
         return STP_EINVAL;
     }
-    if (ctx->cfg.precision == STP_MIXED) CHK(plane_stats(ctx->g, ctx->u, ctx->v, ctx->w, ctx->nut32, ctx->part, ctx->s));
+    if (!ctx->nut) CHK(plane_stats(ctx->g, ctx->u, ctx->v, ctx->w, ctx->nut32, ctx->part, ctx->s));
     else CHK(plane_stats(ctx->g, ctx->u, ctx->v, ctx->w, ctx->nut, ctx->part, ctx->s));
     CHK(hipMemcpyAsync(out, ctx->part, count * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
     CHK(hipStreamSynchronize(ctx->s));

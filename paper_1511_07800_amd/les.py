@@ -53,6 +53,7 @@ def main(argv=None):
     ap.add_argument("--save", default=None)
     ap.add_argument("--restart", default=None)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--stencils32", type=int, default=0, help="eddy viscosity and explicit terms in FP32")
     ap.add_argument("--max-seconds", type=float, default=None,
                     help="stop stepping after this much wall time (then save and report)")
     args = ap.parse_args(argv)
@@ -66,7 +67,7 @@ def main(argv=None):
     torch.cuda.set_device(0)
     ch = Channel(*g, nu=wl["nu"], dpdx=wl["dpdx"], dt=wl["dt"], les=1, cs=wl["cs"], vd_a=wl["vd_a"],
                  precision=STP_MIXED, poisson_rtol=rtol, poisson_maxit=200, srj_adaptive=1,
-                 srj_reduction=wl["srj_reduction"], proj_depth=8, mixed_rhs16=1)
+                 srj_reduction=wl["srj_reduction"], proj_depth=8, mixed_rhs16=1, stencils32=args.stencils32)
     t0_sim, acc, nacc, series = 0.0, None, 0, []
     if args.restart:
         z = np.load(args.restart, allow_pickle=False)

@@ -62,6 +62,11 @@ def test_workspace_bytes_valid_and_invalid():
     # the FP16 right-hand side of the mixed passes: nx*ny*nz halves
     mixed = lib.stp_workspace_bytes(ctypes.byref(cfg(precision=1)))
     assert lib.stp_workspace_bytes(ctypes.byref(cfg(precision=1, mixed_rhs16=1))) == mixed + 2 * n
+    # FP32 stencils: nu_T and the nine Adams-Bashforth arrays in FP32 instead of
+    # FP64, plus FP32 copies of u, v, w and the nz plane means of u (one
+    # 256-byte aligned block here)
+    nw = 32 * 16 * 17
+    assert lib.stp_workspace_bytes(ctypes.byref(cfg(precision=1, stencils32=1))) == mixed - 24 * n - 8 * nw + 256
     # the least-squares guess keeps proj_depth solutions and their right-hand sides
     for depth in (1, 8):
         assert lib.stp_workspace_bytes(ctypes.byref(cfg(proj_depth=depth))) == n_ok + 2 * depth * 8 * n
@@ -70,7 +75,7 @@ def test_workspace_bytes_valid_and_invalid():
                 dict(les=2), dict(tblock=-1), dict(tblock=6), dict(cn_tol=2.0), dict(srj_m=4),
                 dict(extrap_order=3), dict(extrap_order=1, warm_start=1), dict(proj_depth=-1),
                 dict(proj_depth=9), dict(proj_depth=2, warm_start=1), dict(mixed_rhs16=1),
-                dict(precision=1, mixed_rhs16=2)):
+                dict(precision=1, mixed_rhs16=2), dict(stencils32=1), dict(precision=1, stencils32=2)):
         assert lib.stp_workspace_bytes(ctypes.byref(cfg(**bad))) == 0, bad
     assert lib.stp_workspace_bytes(None) == 0
 

@@ -180,18 +180,19 @@ def les256_oracle_trajectory():
     return wl, g, (u, v, w), traj
 
 
-@pytest.mark.parametrize("rhs16", [0, 1])
-def test_mixed_les_256x128x128_against_fp64_oracle(gpu, les256_oracle_trajectory, rhs16):
+@pytest.mark.parametrize("rhs16,st32", [(0, 0), (1, 0), (1, 1)])
+def test_mixed_les_256x128x128_against_fp64_oracle(gpu, les256_oracle_trajectory, rhs16, st32):
     """Mixed mode (FP32 sweeps and Crank-Nicolson increments inside FP64
     defect corrections; with rhs16 each pass reads its right-hand side as
-    FP16) against the FP64 oracle, both converged to rtol 1e-12, on the
+    FP16, with st32 the eddy viscosity and explicit terms run in FP32)
+    against the FP64 oracle, both converged to rtol 1e-12, on the
     256 x 128 x 128 LES workload: the error of every field after each of
     three steps is reported and stays below 1e-5."""
     from paper_1511_07800_amd import Channel, STP_MIXED
     wl, g, (u, v, w), traj = les256_oracle_trajectory
     ch = Channel(*g, nu=wl["nu"], dpdx=wl["dpdx"], dt=wl["dt"], les=1, precision=STP_MIXED,
                  poisson_rtol=1e-12, poisson_maxit=100, srj_adaptive=1, srj_reduction=wl["srj_reduction"],
-                 mixed_rhs16=rhs16)
+                 mixed_rhs16=rhs16, stencils32=st32)
     load_state(ch, u, v, w)
     worst = 0.0
     for n, ref in enumerate(traj):
@@ -199,7 +200,7 @@ def test_mixed_les_256x128x128_against_fp64_oracle(gpu, les256_oracle_trajectory
         assert st["poisson"]["relres"] <= 1e-12
         f = fields(ch)
         errs = {k: rel_l2(f[k], ref[k]) for k in ref}
-        print(f"mixed (rhs16={rhs16}) step {n + 1}: passes {st['poisson']['outer']} "
+        print(f"mixed (rhs16={rhs16}, stencils32={st32}) step {n + 1}: passes {st['poisson']['outer']} "
               + " ".join(f"{k} {e:.2e}" for k, e in errs.items()), flush=True)
         worst = max(worst, max(errs.values()))
     assert worst <= 1e-5

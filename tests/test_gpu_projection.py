@@ -22,12 +22,13 @@ pytestmark = pytest.mark.gpu
 G = dict(nx=128, ny=64, nz=64, lx=4 * math.pi, ly=2 * math.pi, lz=2.0, nu=1.0 / 180, dpdx=-1.0, dt=4e-5)
 
 
-def channel(proj_depth=0, extrap_order=0, precision=1, rtol=1e-8, g=G, maxit=200, rhs16=0):
+def channel(proj_depth=0, extrap_order=0, precision=1, rtol=1e-8, g=G, maxit=200, rhs16=0, stencils32=0):
     import torch
     from paper_1511_07800_amd import Channel
     ch = Channel(g["nx"], g["ny"], g["nz"], g["lx"], g["ly"], g["lz"], nu=g["nu"], dpdx=g["dpdx"], dt=g["dt"],
                  les=1, precision=precision, poisson_rtol=rtol, poisson_maxit=maxit, srj_adaptive=1,
-                 srj_reduction=1e-4, extrap_order=extrap_order, proj_depth=proj_depth, mixed_rhs16=rhs16)
+                 srj_reduction=1e-4, extrap_order=extrap_order, proj_depth=proj_depth, mixed_rhs16=rhs16,
+                 stencils32=stencils32)
     u, v, w = inputs.channel_state(g["nx"], g["ny"], g["nz"], g["lz"], g["nu"], g["dpdx"], noise=0.1, seed=7901)
     for k, a in enumerate((u, v, w)):
         ch.field(k).copy_(torch.from_numpy(a))
@@ -126,13 +127,14 @@ def test_step_guess_is_least_squares_and_least_residual(gpu, depth, precision):
     ch.close()
 
 
-def test_projection_keeps_tolerance_and_saves_sweeps(gpu):
+@pytest.mark.parametrize("st32", [0, 1])
+def test_projection_keeps_tolerance_and_saves_sweeps(gpu, st32):
     import torch
     from paper_1511_07800_amd import STP_U, STP_V, STP_W, STP_P
-    print("least-squares guess vs p^n and extrapolation, mixed", flush=True)
+    print(f"least-squares guess vs p^n and extrapolation, mixed, stencils32={st32}", flush=True)
     sweeps, out = {}, {}
     for name, kw in (("prev", {}), ("extrap", dict(extrap_order=2)), ("lsq", dict(proj_depth=8))):
-        ch = channel(**kw)
+        ch = channel(stencils32=st32, **kw)
         sw = []
         for _ in range(16):
             st = ch.step(1)
@@ -142,14 +144,15 @@ def test_projection_keeps_tolerance_and_saves_sweeps(gpu):
         out[name] = [ch.field(k).clone() for k in (STP_U, STP_V, STP_W, STP_P)]
         ch.close()
     print("sweeps", sweeps, flush=True)
-    # Velocities agree to the solver tolerance.  The mixed mode evaluates the
-    # explicit terms in FP32, so the two runs' divergence sources differ by
-    # FP32 rounding of those terms (~1e-7 relative), which the smooth pressure
-    # modes amplify: p is held to the mixed-mode bar against FP64, 1e-5.
+    # Velocities agree to the solver tolerance, and p to the tolerance times the
+    # conditioning of its smooth modes (1e-6).  With stencils32 the explicit
+    # terms are evaluated in FP32, so the two runs' divergence sources differ
+    # by FP32 rounding of those terms (~1e-7 relative), which the smooth
+    # pressure modes amplify: p is then held to the mixed-mode bar, 1e-5.
     for fname, a, r in zip("uvwp", out["lsq"], out["prev"]):
         err = float((a - r).norm() / r.norm())
         print(fname, f"{err:.2e}", flush=True)
-        assert err <= (1e-5 if fname == "p" else 1e-8)
+        assert err <= ((1e-5 if st32 else 1e-6) if fname == "p" else 1e-8)
     assert sum(sweeps["lsq"][-8:]) < sum(sweeps["extrap"][-8:]) < sum(sweeps["prev"][-8:])
 
 

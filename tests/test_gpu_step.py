@@ -14,12 +14,12 @@ from _helpers import rel_l2, load_state, fields
 pytestmark = pytest.mark.gpu
 
 
-def make_pair(g, nu, dpdx, dt, les, rtol, maxit, u, v, w, precision=0, warm=0):
+def make_pair(g, nu, dpdx, dt, les, rtol, maxit, u, v, w, precision=0, warm=0, **kw):
     from paper_1511_07800_amd import Channel
     nx, ny, nz, lx, ly, lz = g
     om = osched.srj_schedule(*g)
     ch = Channel(nx, ny, nz, lx, ly, lz, nu=nu, dpdx=dpdx, dt=dt, les=les, precision=precision,
-                 warm_start=warm, poisson_rtol=rtol, poisson_maxit=maxit, omega=list(om))
+                 warm_start=warm, poisson_rtol=rtol, poisson_maxit=maxit, omega=list(om), **kw)
     load_state(ch, u, v, w)
     P = oracle.make_params(nx, ny, nz, lx, ly, lz, nu=nu, dpdx=dpdx, dt=dt, les=les)
     orc = oracle.Solver(P, u, v, w, omega=om, rtol=rtol, maxit=maxit, warm_start="zero" if warm else "prev")
@@ -106,14 +106,16 @@ def test_les_converged_same_stop_cycles(gpu):
     compare(ch, orc, 1e-10)
 
 
-def test_mixed_les_against_fp64_oracle(gpu):
-    """Mixed mode (FP32 sweeps, FP64 residual and correction) after 10 LES
-    steps stays within 1e-5 of the FP64 oracle converged to 1e-12."""
+@pytest.mark.parametrize("st32", [0, 1])
+def test_mixed_les_against_fp64_oracle(gpu, st32):
+    """Mixed mode (FP32 sweeps, FP64 residual and correction; with st32 the
+    eddy viscosity and explicit terms in FP32 too) after 10 LES steps stays
+    within 1e-5 of the FP64 oracle converged to 1e-12."""
     from paper_1511_07800_amd import STP_MIXED
     g = (48, 32, 24, 2 * math.pi, math.pi, 2.0)
     nx, ny, nz, lx, ly, lz = g
     u, v, w = inputs.channel_state(nx, ny, nz, lz, 1 / 180, -1.0, noise=0.1, seed=34)
-    ch, orc = make_pair(g, 1 / 180, -1.0, 2e-5, 1, 1e-12, 100, u, v, w, precision=STP_MIXED)
+    ch, orc = make_pair(g, 1 / 180, -1.0, 2e-5, 1, 1e-12, 100, u, v, w, precision=STP_MIXED, stencils32=st32)
     errs = []
     for n in range(10):
         st = ch.step(1)
@@ -122,7 +124,7 @@ def test_mixed_les_against_fp64_oracle(gpu):
         errs.append(max(rel_l2(f[k], getattr(orc, k)) for k in ("u", "v", "w", "p")))
         # div u^{n+1} = dt (b - L p) holds in FP64 for the mixed result too
         assert st["max_div"] <= 2e-5 * st["poisson"]["relres"] * st["poisson"]["bnorm"] * 1.001 + 1e-13
-    print("mixed error by step", " ".join(f"{e:.2e}" for e in errs))
+    print(f"mixed (stencils32={st32}) error by step", " ".join(f"{e:.2e}" for e in errs))
     assert max(errs) <= 1e-5
 
 
@@ -199,8 +201,9 @@ def test_bad_config_rejected(gpu):
 
 
 def test_mixed_mode_eddy_viscosity_in_fp32(gpu):
-    """The mixed mode computes nu_T from FP32 copies of the state and keeps it
-    in FP32 (stp_fields reports the FP32 array): after one step it equals the
+    """With stencils32 the mixed mode computes nu_T from FP32 copies of the
+    state (u as its departure from the plane means) and keeps it in FP32
+    (stp_fields reports the FP32 array): after one step it equals the
     oracle's FP64 nu_T of the starting state to FP32 precision of the strain
     (1e-5 of the largest eddy-viscosity increment), and the step's maximum
     agrees likewise."""
@@ -209,7 +212,7 @@ def test_mixed_mode_eddy_viscosity_in_fp32(gpu):
     g = (48, 32, 24, 2 * math.pi, math.pi, 2.0)
     nx, ny, nz, lx, ly, lz = g
     u, v, w = inputs.channel_state(nx, ny, nz, lz, 1 / 180, -1.0, noise=0.1, seed=37)
-    ch, _ = make_pair(g, 1 / 180, -1.0, 2e-5, 1, 0.0, 1, u, v, w, precision=STP_MIXED)
+    ch, _ = make_pair(g, 1 / 180, -1.0, 2e-5, 1, 0.0, 1, u, v, w, precision=STP_MIXED, stencils32=1)
     st = ch.step(1)
     nut = ch.field(STP_NUT)
     assert nut.dtype == torch.float32
