@@ -168,19 +168,14 @@ __device__ __forceinline__ T buf_load_rhs(__amdgpu_buffer_rsrc_t r, unsigned off
         return buf_load<T>(r, off);
     }
 }
-// AUX is the store's cache policy: 0 ordinary, kStoreStream nontemporal
-// (the line is written through without being kept in the caches)
-constexpr int kStoreStream = 2;
-template <int AUX = 0>
 __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, AUX);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
-template <int AUX = 0>
 __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off)
 {
     typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, AUX);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
 
 // value of the lane below / above in the wavefront (DPP wave shifts); the
@@ -220,8 +215,7 @@ __device__ __forceinline__ void unrolled(int t0, F& f, std::integer_sequence<int
 template <typename T>
 constexpr int kMinWavesPerSimd = sizeof(T) == 4 ? 4 : 1;
 
-// STREAM: write the result with nontemporal stores (see launch_fused)
-template <typename T, typename TB, int NT, int WAVES, bool STREAM>
+template <typename T, typename TB, int NT, int WAVES>
 __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused(int nx, int ny, int nz, int zchunk,
                                                             int tx, int ty, int ntiles,
                                                             const TB* __restrict__ b, const T* __restrict__ p,
@@ -374,8 +368,7 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
 #pragma unroll
                 for (int m = 0; m < PTS; ++m) {
                     const int r = row[m];
-                    if (r >= NT && r < kRows - NT && y0 + r < ny)
-                        buf_store<STREAM ? kStoreStream : 0>(res[m], ro, col[m]);
+                    if (r >= NT && r < kRows - NT && y0 + r < ny) buf_store(res[m], ro, col[m]);
                 }
             }
         }
@@ -394,8 +387,8 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
     for (int tb = t_begin; tb <= t_end; tb += kUnroll) unrolled(tb, step, std::make_integer_sequence<int, kUnroll>{});
 }
 
-// Workgroups of k_relax_fused<T, TB, NT, WAVES, STREAM> resident on the device at once.
-template <typename T, typename TB, int NT, int WAVES, bool STREAM>
+// Workgroups of k_relax_fused<T, TB, NT, WAVES> resident on the device at once.
+template <typename T, typename TB, int NT, int WAVES>
 int resident_workgroups()
 {
     static int cached = 0;  // per kernel instance; one device model per process
@@ -403,21 +396,21 @@ int resident_workgroups()
         int dev = 0, cus = 0, per_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_relax_fused<T, TB, NT, WAVES, STREAM>, 64 * WAVES,
-                                                         0) != hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_relax_fused<T, TB, NT, WAVES>, 64 * WAVES, 0) !=
+                hipSuccess)
             return 0;
         cached = std::max(1, cus * per_cu);
     }
     return cached;
 }
 
-template <typename T, typename TB, int NT, int WAVES, bool STREAM>
-hipError_t launch_fused_as(const Geo& g, const TB* b, const T* p, T* out, const Weights& wts, hipStream_t s)
+template <typename T, typename TB, int NT, int WAVES>
+hipError_t launch_fused(const Geo& g, const TB* b, const T* p, T* out, const Weights& wts, hipStream_t s)
 {
     constexpr int OX = kTileX - 2 * NT, OY = kRows - 2 * NT;
     const int tx = (g.nx + OX - 1) / OX, ty = (g.ny + OY - 1) / OY;
     const long long tiles = (long long)tx * ty;
-    const int resident = resident_workgroups<T, TB, NT, WAVES, STREAM>();
+    const int resident = resident_workgroups<T, TB, NT, WAVES>();
     if (resident == 0) return hipErrorInvalidDevice;
     // z-chunks: the fewest rounds of resident workgroups times steps per
     // chunk (a chunk of zc planes takes zc + 2 NT steps)
@@ -435,25 +428,9 @@ hipError_t launch_fused_as(const Geo& g, const TB* b, const T* p, T* out, const 
     nzc = (g.nz + zchunk - 1) / zchunk;
     const int ntiles = (int)(tiles * nzc);
     const int grid = (ntiles + kXcds - 1) / kXcds * kXcds;  // whole rounds over the XCDs
-    hipLaunchKernelGGL((k_relax_fused<T, TB, NT, WAVES, STREAM>), dim3(grid), dim3(64 * WAVES), 0, s, g.nx, g.ny, g.nz,
-                       zchunk, tx, ty, ntiles, b, p, out, stage_coefs<T>(g, wts, NT));
+    hipLaunchKernelGGL((k_relax_fused<T, TB, NT, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, g.nx, g.ny, g.nz, zchunk,
+                       tx, ty, ntiles, b, p, out, stage_coefs<T>(g, wts, NT));
     return hipGetLastError();
-}
-
-// The result array is written once and read only by the next launch.  When
-// what a launch reads (p and b) fits in the 256 MiB Infinity Cache of an
-// MI355X, writing the result past the caches keeps p and b cached for the
-// next launch of the cycle (measured: 82 -> 74 us per launch at 512x256x192,
-// 23.7 -> 22.9 us at 256x128x128); on larger grids nothing stays cached
-// between launches and ordinary stores are as fast or faster (1024x512x384).
-constexpr long long kInfinityCacheBytes = 256LL << 20;
-
-template <typename T, typename TB, int NT, int WAVES>
-hipError_t launch_fused(const Geo& g, const TB* b, const T* p, T* out, const Weights& wts, hipStream_t s)
-{
-    if (g.n * (long long)(sizeof(T) + sizeof(TB)) <= kInfinityCacheBytes)
-        return launch_fused_as<T, TB, NT, WAVES, true>(g, b, p, out, wts, s);
-    return launch_fused_as<T, TB, NT, WAVES, false>(g, b, p, out, wts, s);
 }
 
 // One sweep per launch, one thread per (i, j) column marching along z with the
