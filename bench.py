@@ -45,6 +45,8 @@ def parse():
     # twice the least-squares history depth, so the timed steps are steady state
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--spinup", type=int, default=16,
+                    help="steps from the noisy laminar start that prepare the input state (untimed; 0: none)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -65,7 +67,10 @@ def parse():
 
 
 def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap_order=0, proj_depth=0,
-                 rhs16=0, stencils32=0):
+                 rhs16=0, stencils32=0, state=None):
+    """A context on the workload, started from `state` (device tensors u, v,
+    w, p from prepare_state) or, without one, from the laminar profile plus
+    the workload's seeded noise."""
     import torch
     from paper_1511_07800_amd import Channel, inputs
     ch = Channel(wl["nx"], wl["ny"], wl["nz"], wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"],
@@ -73,6 +78,11 @@ def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap
                  poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=0 if FIXED_CYCLES else 1,
                  srj_reduction=wl.get("srj_reduction", 1e-3), learned_correction=learned_correction,
                  extrap_order=extrap_order, proj_depth=proj_depth, mixed_rhs16=rhs16, stencils32=stencils32)
+    if state is not None:
+        for k, a in enumerate(state):
+            ch.field(k).copy_(a)
+        torch.cuda.synchronize()
+        return ch
     u, v, w = inputs.channel_state(wl["nx"], wl["ny"], wl["nz"], wl["lz"], wl["nu"], wl["dpdx"],
                                    noise=wl.get("noise", 0.0), seed=wl.get("seed", 0))
     for k, a in enumerate((u, v, w)):
@@ -80,6 +90,31 @@ def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap
     del u, v, w
     torch.cuda.synchronize()
     return ch
+
+
+def prepare_state(wl, args):
+    """The benchmark's input state: the laminar profile plus seeded noise,
+    advanced args.spinup steps (mixed precision, least-squares guess) before
+    anything is timed, so that every variant starts from the same developed
+    flow rather than from the start-up transient of the noisy laminar state
+    (whose non-solenoidal noise and fast early pressure changes would make the
+    first few dozen steps unrepresentative of a running LES).  Returns device
+    copies of u, v, w and p, or None for args.spinup = 0."""
+    import torch
+    from paper_1511_07800_amd import STP_MIXED
+    if args.spinup <= 0:
+        return None
+    ch = make_channel(wl, STP_MIXED, args.rtol, proj_depth=PROJ_DEPTH)
+    for i in range(args.spinup):
+        st = ch.step(1)
+        print(f"[input preparation] step {i + 1}/{args.spinup}: sweeps {st['poisson']['sweeps']} "
+              f"relres0 {st['poisson']['relres0']:.2e}", file=sys.stderr, flush=True)
+    state = [ch.field(k).clone() for k in range(4)]
+    torch.cuda.synchronize()
+    ch.close()
+    del ch
+    torch.cuda.empty_cache()
+    return state
 
 
 PHASES = ("ms_nut", "ms_momentum", "ms_divergence", "ms_guess", "ms_poisson", "ms_projection")
@@ -357,7 +392,7 @@ EXTRA_VARIANTS = [
 ]
 
 
-def run_variant(wl, args, name, precision, opt):
+def run_variant(wl, args, name, precision, opt, state=None):
     import torch
     from paper_1511_07800_amd import STP_FP64, STP_MIXED, STP_WS_LEARNED, STP_WS_PREV, warmstart
     learned = opt.get("learned", False)
@@ -365,7 +400,7 @@ def run_variant(wl, args, name, precision, opt):
                       warm_start=STP_WS_LEARNED if learned else STP_WS_PREV,
                       learned_correction=opt.get("correction", 0), extrap_order=opt.get("extrap_order", 0),
                       proj_depth=opt.get("proj_depth", 0), rhs16=opt.get("rhs16", 0),
-                      stencils32=opt.get("stencils32", 0))
+                      stencils32=opt.get("stencils32", 0), state=state)
     weights = None
     if learned:
         ch.net_init(training=False)
@@ -412,9 +447,11 @@ def main():
     if args.profile_kernels:
         profile_kernels(wl)
         return
+    state = prepare_state(wl, args)
     if args.profile_fastest:
         from paper_1511_07800_amd import STP_WS_LEARNED, warmstart
-        ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED, proj_depth=PROJ_DEPTH, rhs16=1)
+        ch = make_channel(wl, STP_MIXED, args.rtol, warm_start=STP_WS_LEARNED, proj_depth=PROJ_DEPTH, rhs16=1,
+                          state=state)
         ch.net_init(training=False)
         warmstart.load_weights(ch, os.path.join(ROOT, "paper_1511_07800_amd", "weights", args.weights))
         t, acc, _, per_step = time_steps(ch, args.steps, args.warmup, "learned+lsq+mixed(rhs16)")
@@ -430,7 +467,7 @@ def main():
     results, fields = {}, {}
     acc_mixed = t_mixed = None
     for name, precision, opt in todo:
-        out, acc, t, f = run_variant(wl, args, name, precision, opt)
+        out, acc, t, f = run_variant(wl, args, name, precision, opt, state)
         results[name] = out
         fields[name] = f
         if name == "mixed":
@@ -439,6 +476,7 @@ def main():
             roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
             if roof["traffic"]:
                 roof["traffic_over_algorithmic"] = round(roof["traffic"] / (12.0 * n), 3)
+    del state
     errors = None
     if "fp64" in fields:
         errors = {k: field_errors(f, fields["fp64"]) for k, f in fields.items() if k != "fp64"}
@@ -456,7 +494,10 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": [wl["nx"], wl["ny"], wl["nz"]], "precision": "mixed",
-                   "poisson_rtol": args.rtol, "dt": wl["dt"], "les": wl["les"], "init": "laminar+10% noise",
+                   "poisson_rtol": args.rtol, "dt": wl["dt"], "les": wl["les"],
+                   "init": (f"laminar + {wl.get('noise', 0.0):g} x U_cl noise, advanced {args.spinup} mixed steps "
+                            "(least-squares guess) as untimed input preparation" if args.spinup > 0
+                            else f"laminar + {wl.get('noise', 0.0):g} x U_cl noise"),
                    "srj_cycles": "fixed 1e-3" if FIXED_CYCLES else "adaptive"},
         "les_steps_per_s": steps_per_s,
         "les_steps_per_s_vs_fp64": ({k: round(v / fp64_rate, 3) for k, v in steps_per_s.items()}
