@@ -161,11 +161,19 @@ def time_steps(ch, steps, warmup, label):
     return dt, acc, st, per_step
 
 
+def fused_depth(acc):
+    """Sweeps per launch of the timed steps' relaxation (the last launch of a
+    cycle may run fewer)."""
+    return -(-acc["sweeps"] // max(acc["launches"], 1))
+
+
 def roofline_from_steps(n, acc, word_bytes, kernel, rhs_bytes=None):
     """Roofline of the dominant kernel from the timed steps: one launch moves
     3 words per cell of compulsory traffic (read p, read b, write p; b takes
     rhs_bytes when stored narrower), so achieved = that per cell x n x
-    launches / device time of the sweep sequences."""
+    launches / device time of the sweep sequences.  `kernel` may hold {d}
+    for the fusion depth."""
+    kernel = kernel.format(d=fused_depth(acc))
     sec = acc["ms_relax"] * 1e-3
     per_cell = 2.0 * word_bytes + (word_bytes if rhs_bytes is None else rhs_bytes)
     achieved = per_cell * n * acc["launches"] / sec / 1e9
@@ -181,7 +189,8 @@ def measured_traffic(nx, ny, nz, tblock):
     """HBM-side bytes per launch of the FP32 relaxation kernel from the
     committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled
     by the same counter on a plain copy of known size); None unless the
-    summary was taken on this kernel source, grid and fusion depth."""
+    summary was taken on this kernel source, grid and fusion depth (tblock
+    sweeps per launch)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "relax_traffic.json")
     src = os.path.join(ROOT, "paper_1511_07800_amd", "csrc", "stp_relax.hip")
@@ -190,16 +199,16 @@ def measured_traffic(nx, ny, nz, tblock):
     rec = json.load(open(path))
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     entry = rec.get("grids", {}).get(f"{nx}x{ny}x{nz}")
-    if rec.get("source_sha256") != sha or entry is None or rec.get("sweeps_per_launch") != tblock:
+    if rec.get("source_sha256") != sha or entry is None or entry.get("sweeps_per_launch") != tblock:
         return None
     return round(entry["hbm_bytes_per_launch"])
 
 
 def profile_kernels(wl):
     """Kernels for counter collection: a torch copy of 64 Mi floats (512 MiB
-    moved: 256 MiB read, 256 MiB written), then 8 launches each of the fused
-    FP32 relaxation kernel, the single-sweep FP32 kernel and the fused kernel
-    with an FP16 right-hand side."""
+    moved: 256 MiB read, 256 MiB written), then 40 sweeps of the fused FP32
+    relaxation kernel at the library's fusion depth, 8 of the single-sweep
+    FP32 kernel and 40 of the fused kernel with an FP16 right-hand side."""
     import torch
     from paper_1511_07800_amd import Channel, inputs
     a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -209,15 +218,16 @@ def profile_kernels(wl):
     torch.cuda.synchronize()
     nx, ny, nz = wl["nx"], wl["ny"], wl["nz"]
     b = torch.from_numpy(inputs.poisson_rhs(nx, ny, nz, seed=1511)).float().cuda()
-    for tb in (4, 1):
+    for tb in (0, 1):  # the library's own fusion depth (4 or 5 on these grids), then single sweeps
         ch = Channel(nx, ny, nz, wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"], dt=wl["dt"], tblock=tb)
         p = torch.zeros_like(b)
         om = ch.schedule()
-        ch.relax(b, p, [om[k % len(om)] for k in range(8 * tb)])
+        nsw = 40 if tb == 0 else 8  # 10 launches of 4 sweeps or 8 of 5
+        ch.relax(b, p, [om[k % len(om)] for k in range(nsw)])
         torch.cuda.synchronize()
-        if tb == 4:
+        if tb == 0:
             p.zero_()
-            ch.relax(b.half(), p, [om[k % len(om)] for k in range(8 * tb)])
+            ch.relax(b.half(), p, [om[k % len(om)] for k in range(nsw)])
             torch.cuda.synchronize()
         ch.close()
     print("profile-kernels done", file=sys.stderr, flush=True)
@@ -421,9 +431,9 @@ def run_variant(wl, args, name, precision, opt, state=None):
     if opt.get("correction"):
         out["corrections_per_step"] = acc["corrections"] / args.steps
     if precision == "fp64":
-        out["relax_kernel"] = roofline_from_steps(n, acc, 8, "k_relax_fused<double,double,4,16>")
+        out["relax_kernel"] = roofline_from_steps(n, acc, 8, "k_relax_fused<double,double,{d},16>")
     elif opt.get("rhs16"):
-        out["relax_kernel"] = roofline_from_steps(n, acc, 4, "k_relax_fused<float,_Float16,4,8>", rhs_bytes=2)
+        out["relax_kernel"] = roofline_from_steps(n, acc, 4, "k_relax_fused<float,_Float16,{d},8>", rhs_bytes=2)
     f = fields_of(ch)
     ch.close()
     del ch
@@ -472,8 +482,8 @@ def main():
         fields[name] = f
         if name == "mixed":
             acc_mixed, t_mixed = acc, t
-            roof = roofline_from_steps(n, acc, 4, "k_relax_fused<float,float,4,8>")
-            roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], 4)
+            roof = roofline_from_steps(n, acc, 4, "k_relax_fused<float,float,{d},8>")
+            roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], fused_depth(acc))
             if roof["traffic"]:
                 roof["traffic_over_algorithmic"] = round(roof["traffic"] / (12.0 * n), 3)
     del state

@@ -161,7 +161,7 @@ class Channel:
 
     def __init__(self, nx, ny, nz, lx, ly, lz, nu, dpdx, dt, les=0, cs=0.1, vd_a=25.0,
                  precision=STP_FP64, warm_start=STP_WS_PREV, poisson_rtol=1e-10, poisson_maxit=1000,
-                 omega=None, srj_reduction=1e-3, mixed_inner=1, tblock=4, cn_tol=1e-13, srj_adaptive=0,
+                 omega=None, srj_reduction=1e-3, mixed_inner=1, tblock=0, cn_tol=1e-13, srj_adaptive=0,
                  learned_correction=0, extrap_order=0, proj_depth=0, mixed_rhs16=0, stencils32=0,
                  device=None):
         import torch

@@ -79,7 +79,6 @@ stp_config effective(const stp_config& c)
     stp_config e = c;
     if (e.srj_reduction == 0.0) e.srj_reduction = 1e-3;
     if (e.mixed_inner == 0) e.mixed_inner = 1;
-    if (e.tblock == 0) e.tblock = 4;
     if (e.cn_tol == 0.0) e.cn_tol = 1e-13;
     return e;
 }
@@ -135,7 +134,7 @@ const char* validate(const stp_config& c)
     if (c.mixed_inner < 1) return "mixed_inner must be >= 1";
     if (c.srj_adaptive != 0 && c.srj_adaptive != 1) return "srj_adaptive must be 0 or 1";
     if (c.srj_adaptive && c.srj_m > 0) return "srj_adaptive needs the built-in schedule (srj_m = 0)";
-    if (c.tblock < 1 || c.tblock > kMaxFused) return "tblock must lie in 1..5";
+    if (c.tblock < 0 || c.tblock > kMaxFused) return "tblock must lie in 0..5";
     if (!(c.cn_tol > 0.0 && c.cn_tol < 1.0)) return "cn_tol must lie in (0, 1)";
     if (c.learned_correction != 0 && c.learned_correction != 1) return "learned_correction must be 0 or 1";
     if (c.extrap_order < 0 || c.extrap_order > 2) return "extrap_order must be 0, 1 or 2";
@@ -343,9 +342,11 @@ template <typename T, typename TB = T>
 stp_status run_sweeps(stp_ctx* ctx, const TB* b, T** cur, T** other, const double* omega, int m, long long first,
                       long long count, int* launches = nullptr)
 {
-    // tblock sweeps per launch where the grid allows it (FP64: at most 4),
-    // the remainder in one shorter launch.
-    const int tb = relax_fusable(ctx->g) ? std::min(ctx->cfg.tblock, sizeof(T) == 4 ? kMaxFused : 4) : 1;
+    // tblock sweeps per launch where the grid allows it (FP64: at most 4;
+    // tblock = 0: FP32 sweeps take relax_auto_depth, FP64 four), the
+    // remainder in one shorter launch.
+    const int want = ctx->cfg.tblock != 0 ? ctx->cfg.tblock : (sizeof(T) == 4 ? relax_auto_depth(ctx->g) : 4);
+    const int tb = relax_fusable(ctx->g) ? std::min(want, sizeof(T) == 4 ? kMaxFused : 4) : 1;
     long long s = 0;
     while (s < count) {
         const int nf = (int)std::min<long long>(tb, count - s);

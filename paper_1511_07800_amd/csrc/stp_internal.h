@@ -121,6 +121,10 @@ hipError_t sum_into(const double* a, long long n, double* part, double* res, int
 // nfused = 1 (any grid) or 2..kMaxFused (FP64: 2..4) on grids with nx >= 64
 // and ny >= 32.
 bool relax_fusable(const Geo& g);
+// FP32 sweeps fused per launch when the caller leaves the choice to the
+// library: 4 when a four-sweep launch fits one round of resident
+// workgroups, else 5 (1 on grids that cannot fuse).
+int relax_auto_depth(const Geo& g);
 template <typename T>
 hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, int nfused, hipStream_t s);
 // FP32 sweeps whose right-hand side is stored in FP16 (widened exactly on load)

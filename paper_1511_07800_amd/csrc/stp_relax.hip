@@ -404,28 +404,43 @@ int resident_workgroups()
     return cached;
 }
 
-template <typename T, typename TB, int NT, int WAVES>
-hipError_t launch_fused(const Geo& g, const TB* b, const T* p, T* out, const Weights& wts, hipStream_t s)
+// Column tiles of a launch fusing NT sweeps
+template <int NT>
+long long tile_count(const Geo& g, int* tx = nullptr, int* ty = nullptr)
 {
     constexpr int OX = kTileX - 2 * NT, OY = kRows - 2 * NT;
-    const int tx = (g.nx + OX - 1) / OX, ty = (g.ny + OY - 1) / OY;
-    const long long tiles = (long long)tx * ty;
-    const int resident = resident_workgroups<T, TB, NT, WAVES>();
-    if (resident == 0) return hipErrorInvalidDevice;
-    // z-chunks: the fewest rounds of resident workgroups times steps per
-    // chunk (a chunk of zc planes takes zc + 2 NT steps)
+    const int x = (g.nx + OX - 1) / OX, y = (g.ny + OY - 1) / OY;
+    if (tx) *tx = x;
+    if (ty) *ty = y;
+    return (long long)x * y;
+}
+
+// Planes per z-chunk: the fewest rounds of resident workgroups times steps
+// per chunk (a chunk of zc planes takes zc + 2 NT steps).
+int zchunk_planes(long long tiles, int nz, int resident, int nt)
+{
     int nzc = 1;
     long long best = -1;
-    for (int k = 1; k <= std::max(1, g.nz / kMinChunk); ++k) {
-        const long long zc = (g.nz + k - 1) / k;
-        const long long cost = (tiles * k + resident - 1) / resident * (zc + 2 * NT);
+    for (int k = 1; k <= std::max(1, nz / kMinChunk); ++k) {
+        const long long zc = (nz + k - 1) / k;
+        const long long cost = (tiles * k + resident - 1) / resident * (zc + 2 * nt);
         if (best < 0 || cost < best) {
             best = cost;
             nzc = k;
         }
     }
-    const int zchunk = (g.nz + nzc - 1) / nzc;
-    nzc = (g.nz + zchunk - 1) / zchunk;
+    return (nz + nzc - 1) / nzc;
+}
+
+template <typename T, typename TB, int NT, int WAVES>
+hipError_t launch_fused(const Geo& g, const TB* b, const T* p, T* out, const Weights& wts, hipStream_t s)
+{
+    int tx = 0, ty = 0;
+    const long long tiles = tile_count<NT>(g, &tx, &ty);
+    const int resident = resident_workgroups<T, TB, NT, WAVES>();
+    if (resident == 0) return hipErrorInvalidDevice;
+    const int zchunk = zchunk_planes(tiles, g.nz, resident, NT);
+    const int nzc = (g.nz + zchunk - 1) / zchunk;
     const int ntiles = (int)(tiles * nzc);
     const int grid = (ntiles + kXcds - 1) / kXcds * kXcds;  // whole rounds over the XCDs
     hipLaunchKernelGGL((k_relax_fused<T, TB, NT, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, g.nx, g.ny, g.nz, zchunk,
@@ -465,6 +480,26 @@ __global__ __launch_bounds__(256) void k_relax(int nx, int ny, int nz, int kchun
 bool relax_fusable(const Geo& g)
 {
     return g.nx >= kTileX && g.ny >= kTileY && (long long)g.nx * g.ny < (1LL << 29);
+}
+
+// When every workgroup of a four-sweep launch is resident at once, the tiles
+// march in z-step and read the halo rows they share through L2, and four
+// sweeps per launch do the least vector work per update; when the launch
+// needs several rounds of workgroups, the halos are fetched once per tile
+// and the kernel is bound by that traffic, which five sweeps per launch
+// spread over one more sweep (measured in the step: 1024x512x384, 658 us per
+// four sweeps against 701 us per five, 14% less time per sweep; 512x256x192,
+// one round, 77 us per four and 96 us per five, and 69 against 96 us with the
+// FP16 right-hand side).
+int relax_auto_depth(const Geo& g)
+{
+    if (!relax_fusable(g)) return 1;
+    const long long tiles = tile_count<4>(g);
+    const int resident = resident_workgroups<float, float, 4, kWaves<float>>();
+    if (resident == 0) return 4;
+    const int zchunk = zchunk_planes(tiles, g.nz, resident, 4);
+    const long long launched = tiles * ((g.nz + zchunk - 1) / zchunk);
+    return launched > resident ? 5 : 4;
 }
 
 template <typename T, typename TB>
