@@ -320,11 +320,14 @@ def oracle_sweeps(P, b, om, seconds):
 
 
 def cpu_baseline(wl):
-    """The FP64 oracle on the host cores, on a bounded sample (about 20 s):
+    """The FP64 oracle on the host cores, on a bounded sample (about 35 s):
     consecutive SRJ sweeps of the workload's grid with all the threads the
-    oracle's OpenMP runtime uses and with one thread, and whole oracle time
-    steps of the 32x16x16 laminar workload (rtol 1e-10) and of the 256x8x128
-    linear-instability workload (the Orr-Sommerfeld wave, rtol 1e-10)."""
+    oracle's OpenMP runtime uses and with one thread, sweeps of the
+    256x128x128 and 512x256x192 grids on all threads, and whole oracle time
+    steps of the 32x16x16 laminar workload (rtol 1e-10), of the 256x8x128
+    linear-instability workload (the Orr-Sommerfeld wave, rtol 1e-10) and of
+    the 256x128x128 LES workload (its first step from the noisy laminar
+    state, rtol 1e-8)."""
     import numpy as np
     import oracle
     from paper_1511_07800_amd import inputs, workloads
@@ -339,6 +342,19 @@ def cpu_baseline(wl):
     nsw1, t_one = oracle_sweeps(P, b, om, 8.0)
     oracle.set_threads(threads)
     del b
+    other_grids = {}
+    for name in ("les_channel_256x128x128", "les_channel_512x256x192"):
+        wg = workloads.params(name)
+        if (wg["nx"], wg["ny"], wg["nz"]) == (nx, ny, nz):
+            continue
+        Pg = oracle.make_params(wg["nx"], wg["ny"], wg["nz"], wg["lx"], wg["ly"], wg["lz"])
+        bg = inputs.poisson_rhs(wg["nx"], wg["ny"], wg["nz"], seed=1511)
+        omg = oracle.srj_schedule(wg["nx"], wg["ny"], wg["nz"], wg["lx"], wg["ly"], wg["lz"])
+        k, tk = oracle_sweeps(Pg, bg, omg, 2.0)
+        other_grids[f"{wg['nx']}x{wg['ny']}x{wg['nz']}"] = {
+            "value": round(k * wg["nx"] * wg["ny"] * wg["nz"] / tk / 1e9, 4), "unit": "Gcell-updates/s",
+            "sweeps": k, "seconds": round(tk, 2)}
+        del bg
     steps = {}
     # whole steps at the small workloads (all threads)
     w0 = workloads.params("laminar_poiseuille_32x16x16")
@@ -365,11 +381,26 @@ def cpu_baseline(wl):
     steps["linear_instability_256x8x128"] = {"ms_per_step": round(1e3 * (time.perf_counter() - t0) / 3, 1),
                                              "steps": 3, "cycles_per_step": [s["poisson_cycles"] for s in st1],
                                              "sweeps_per_cycle": len(s1.omega)}
+    del s1, u, v, w
+    w2 = workloads.params("les_channel_256x128x128")
+    u, v, w = inputs.channel_state(w2["nx"], w2["ny"], w2["nz"], w2["lz"], w2["nu"], w2["dpdx"], noise=w2["noise"],
+                                   seed=w2["seed"])
+    P2 = oracle.make_params(w2["nx"], w2["ny"], w2["nz"], w2["lx"], w2["ly"], w2["lz"], nu=w2["nu"],
+                            dpdx=w2["dpdx"], dt=w2["dt"], les=1)
+    s2 = oracle.Solver(P2, u, v, w, rtol=w2["poisson_rtol"], maxit=200)
+    t0 = time.perf_counter()
+    st2 = s2.step()
+    steps["les_channel_256x128x128"] = {"ms_per_step": round(1e3 * (time.perf_counter() - t0), 1), "steps": 1,
+                                        "cycles_per_step": [st2["poisson_cycles"]],
+                                        "sweeps_per_cycle": len(s2.omega),
+                                        "note": "first step from the noisy laminar state (the solve starts at p = 0)"}
+    del s2, u, v, w
     return {"value": round(nsw * n / t_all / 1e9, 4), "unit": "Gcell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{nsw} consecutive FP64 SRJ sweeps of the {nx}x{ny}x{nz} grid on {threads} threads "
-                      f"({t_all:.1f} s, OpenMP over z-planes); also {nsw1} on 1 thread and whole oracle steps "
-                      f"of the two small workloads",
+                      f"({t_all:.1f} s, OpenMP over z-planes); also {nsw1} on 1 thread, sweeps of the smaller LES "
+                      f"grids and whole oracle steps of three small workloads",
+            "other_grids": other_grids,
             "one_thread": {"value": round(nsw1 * n / t_one / 1e9, 4), "unit": "Gcell-updates/s", "sweeps": nsw1,
                            "seconds": round(t_one, 2)},
             "nproc": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count(),
@@ -403,6 +434,7 @@ EXTRA_VARIANTS = [
 
 
 def run_variant(wl, args, name, precision, opt, state=None):
+    import numpy as np
     import torch
     from paper_1511_07800_amd import STP_FP64, STP_MIXED, STP_WS_LEARNED, STP_WS_PREV, warmstart
     learned = opt.get("learned", False)
@@ -420,6 +452,8 @@ def run_variant(wl, args, name, precision, opt, state=None):
     n = wl["nx"] * wl["ny"] * wl["nz"]
     out = {"steps_per_s": round(args.steps / t, 4), "ms_per_step": round(1e3 * t / args.steps, 2),
            "sweeps_per_step": acc["sweeps"] / args.steps,
+           "sweeps_p95": float(np.percentile([r["sweeps"] for r in per_step], 95)),
+           "relres0_mean": float(np.mean([r["relres0"] for r in per_step])),
            "gcell_updates_per_s": round(acc["sweeps"] * n / t / 1e9, 2), "warmup": args.warmup,
            "phase_ms_per_step": {k[3:]: round(v / args.steps, 2) for k, v in acc["phases"].items()},
            "per_step": per_step}
