@@ -115,11 +115,11 @@ typedef struct {
     int32_t srj_adaptive;      /* built-in schedule only: 0 repeats the srj_reduction cycle; 1 sizes each
                                   cycle from the reduction still needed (see stp_poisson_solve) */
     int32_t tblock;            /* sweeps fused per relaxation launch: 1..5 (FP64 sweeps fuse at most 4), or
-                                  0: the library chooses, FP32 sweeps fusing 4 when a four-sweep launch
-                                  fits one round of resident workgroups (the tiles then share their halo
-                                  rows through L2) and 5 otherwise, FP64 sweeps 4; grids with nx < 64 or
-                                  ny < 32 always run single sweeps.  Results are bitwise identical for
-                                  every value. */
+                                  0: the library chooses, FP32 sweeps fusing 5 on grids with ny >= 66 (tiles
+                                  of 16 wavefronts x 64 rows) and otherwise 4 when a four-sweep launch fits
+                                  one round of resident workgroups, else 5; FP64 sweeps fuse 4.  Grids with
+                                  nx < 64 or ny < 32 always run single sweeps.  Results are bitwise
+                                  identical for every value. */
     double cn_tol;             /* Crank-Nicolson iteration error target relative to the start (e.g. 1e-13) */
     int32_t learned_correction; /* mixed mode with stp_net_init: after each defect-correction pass that has
                                    not converged, try p + s_r y(r, p) from the network (a coarse

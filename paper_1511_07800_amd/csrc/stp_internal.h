@@ -122,8 +122,9 @@ hipError_t sum_into(const double* a, long long n, double* part, double* res, int
 // and ny >= 32.
 bool relax_fusable(const Geo& g);
 // FP32 sweeps fused per launch when the caller leaves the choice to the
-// library: 4 when a four-sweep launch fits one round of resident
-// workgroups, else 5 (1 on grids that cannot fuse).
+// library: 5 where the tall five-sweep tiles fit (ny >= 66); on narrower
+// grids 4 when a four-sweep launch fits one round of resident workgroups,
+// else 5 (1 on grids that cannot fuse).
 int relax_auto_depth(const Geo& g);
 template <typename T>
 hipError_t relax(const Geo& g, const T* b, const T* p, T* out, const Weights& wts, int nfused, hipStream_t s);

@@ -39,13 +39,18 @@ namespace {
 
 constexpr int kTileX = 64;  // one wavefront across x
 constexpr int kTileY = 32;  // rows updated by a workgroup; two more halo rows are only loaded
-constexpr int kRows = kTileY + 2;
 constexpr int kMinChunk = 8;  // planes per z-chunk, at least
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X, each with its own L2
 // wavefronts per workgroup (kTileY / waves rows per thread): measured best
 // 8 for FP32 (two workgroups per CU under the 128-VGPR cap) and 16 for FP64
 template <typename T>
 constexpr int kWaves = sizeof(T) == 4 ? 8 : 16;
+// Five FP32 sweeps per launch run on taller tiles: 16 wavefronts of 4 rows
+// (64 updated rows, one workgroup per CU), whose halo is a smaller share of
+// the tile than with 8 wavefronts (64x66 loaded for 54x56 written, against
+// 64x34 for 54x24).
+constexpr bool kWide5 = true;
+constexpr int kWide5Rows = 64;
 
 // Coefficients of one weighted Jacobi sweep, from omega and D = 2/dx^2 +
 // 2/dy^2 + 2/dz^2:  p + (omega/D)(L_p p - b)
@@ -215,12 +220,14 @@ __device__ __forceinline__ void unrolled(int t0, F& f, std::integer_sequence<int
 template <typename T>
 constexpr int kMinWavesPerSimd = sizeof(T) == 4 ? 4 : 1;
 
-template <typename T, typename TB, int NT, int WAVES>
+// TY: rows a workgroup updates (two more halo rows are only loaded)
+template <typename T, typename TB, int NT, int WAVES, int TY>
 __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused(int nx, int ny, int nz, int zchunk,
                                                             int tx, int ty, int ntiles,
                                                             const TB* __restrict__ b, const T* __restrict__ p,
                                                             T* __restrict__ out, StageCoefs<T> kc)
 {
+    constexpr int kTileY = TY, kRows = TY + 2;
     // Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD
     // w mod 8).  Tile L = (w mod 8) * (grid / 8) + w / 8 gives every XCD a
     // contiguous run of tiles (x fastest, then y, then z-chunk), so the halo
@@ -387,8 +394,8 @@ __global__ __launch_bounds__(64 * WAVES, kMinWavesPerSimd<T>) void k_relax_fused
     for (int tb = t_begin; tb <= t_end; tb += kUnroll) unrolled(tb, step, std::make_integer_sequence<int, kUnroll>{});
 }
 
-// Workgroups of k_relax_fused<T, TB, NT, WAVES> resident on the device at once.
-template <typename T, typename TB, int NT, int WAVES>
+// Workgroups of k_relax_fused<T, TB, NT, WAVES, TY> resident on the device at once.
+template <typename T, typename TB, int NT, int WAVES, int TY>
 int resident_workgroups()
 {
     static int cached = 0;  // per kernel instance; one device model per process
@@ -396,19 +403,19 @@ int resident_workgroups()
         int dev = 0, cus = 0, per_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_relax_fused<T, TB, NT, WAVES>, 64 * WAVES, 0) !=
-                hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_relax_fused<T, TB, NT, WAVES, TY>, 64 * WAVES,
+                                                         0) != hipSuccess)
             return 0;
         cached = std::max(1, cus * per_cu);
     }
     return cached;
 }
 
-// Column tiles of a launch fusing NT sweeps
-template <int NT>
+// Column tiles of a launch fusing NT sweeps over tiles of TY + 2 rows
+template <int NT, int TY = kTileY>
 long long tile_count(const Geo& g, int* tx = nullptr, int* ty = nullptr)
 {
-    constexpr int OX = kTileX - 2 * NT, OY = kRows - 2 * NT;
+    constexpr int OX = kTileX - 2 * NT, OY = TY + 2 - 2 * NT;
     const int x = (g.nx + OX - 1) / OX, y = (g.ny + OY - 1) / OY;
     if (tx) *tx = x;
     if (ty) *ty = y;
@@ -432,19 +439,19 @@ int zchunk_planes(long long tiles, int nz, int resident, int nt)
     return (nz + nzc - 1) / nzc;
 }
 
-template <typename T, typename TB, int NT, int WAVES>
+template <typename T, typename TB, int NT, int WAVES, int TY = kTileY>
 hipError_t launch_fused(const Geo& g, const TB* b, const T* p, T* out, const Weights& wts, hipStream_t s)
 {
     int tx = 0, ty = 0;
-    const long long tiles = tile_count<NT>(g, &tx, &ty);
-    const int resident = resident_workgroups<T, TB, NT, WAVES>();
+    const long long tiles = tile_count<NT, TY>(g, &tx, &ty);
+    const int resident = resident_workgroups<T, TB, NT, WAVES, TY>();
     if (resident == 0) return hipErrorInvalidDevice;
     const int zchunk = zchunk_planes(tiles, g.nz, resident, NT);
     const int nzc = (g.nz + zchunk - 1) / zchunk;
     const int ntiles = (int)(tiles * nzc);
     const int grid = (ntiles + kXcds - 1) / kXcds * kXcds;  // whole rounds over the XCDs
-    hipLaunchKernelGGL((k_relax_fused<T, TB, NT, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, g.nx, g.ny, g.nz, zchunk,
-                       tx, ty, ntiles, b, p, out, stage_coefs<T>(g, wts, NT));
+    hipLaunchKernelGGL((k_relax_fused<T, TB, NT, WAVES, TY>), dim3(grid), dim3(64 * WAVES), 0, s, g.nx, g.ny, g.nz,
+                       zchunk, tx, ty, ntiles, b, p, out, stage_coefs<T>(g, wts, NT));
     return hipGetLastError();
 }
 
@@ -482,20 +489,24 @@ bool relax_fusable(const Geo& g)
     return g.nx >= kTileX && g.ny >= kTileY && (long long)g.nx * g.ny < (1LL << 29);
 }
 
-// When every workgroup of a four-sweep launch is resident at once, the tiles
-// march in z-step and read the halo rows they share through L2, and four
-// sweeps per launch do the least vector work per update; when the launch
-// needs several rounds of workgroups, the halos are fetched once per tile
-// and the kernel is bound by that traffic, which five sweeps per launch
-// spread over one more sweep (measured in the step: 1024x512x384, 658 us per
-// four sweeps against 701 us per five, 14% less time per sweep; 512x256x192,
-// one round, 77 us per four and 96 us per five, and 69 against 96 us with the
-// FP16 right-hand side).
+// The fusion depth for FP32 sweeps.  Five sweeps per launch on the tall
+// 16-wavefront tiles are the fastest wherever those tiles fit the grid
+// (measured in the step: 512x256x192, 18.3 us per sweep against 19.2 with
+// four per launch on 8-wavefront tiles, 17.3 against 17.8 with the FP16
+// right-hand side; 1024x512x384, 139 us per sweep against 164, and 118
+// against 137 on 8-wavefront five-sweep tiles with the FP16 right-hand
+// side).  On grids too narrow for them: when every workgroup of a four-sweep
+// launch is resident at once, the tiles march in z-step and read the halo
+// rows they share through L2, and four sweeps per launch do the least vector
+// work per update; when the launch needs several rounds of workgroups, the
+// halos are fetched once per tile and five sweeps per launch spread that
+// traffic over one more sweep.
 int relax_auto_depth(const Geo& g)
 {
     if (!relax_fusable(g)) return 1;
+    if (kWide5 && g.ny >= kWide5Rows + 2) return 5;
     const long long tiles = tile_count<4>(g);
-    const int resident = resident_workgroups<float, float, 4, kWaves<float>>();
+    const int resident = resident_workgroups<float, float, 4, kWaves<float>, kTileY>();
     if (resident == 0) return 4;
     const int zchunk = zchunk_planes(tiles, g.nz, resident, 4);
     const long long launched = tiles * ((g.nz + zchunk - 1) / zchunk);
@@ -518,7 +529,10 @@ hipError_t relax_impl(const Geo& g, const TB* b, const T* p, T* out, const Weigh
     case 4: return launch_fused<T, TB, 4, kWaves<T>>(g, b, p, out, wts, s);
     }
     if constexpr (sizeof(T) == 4) {  // FP64 rings do not fit deeper pipelines in registers
-        if (nfused == 5) return launch_fused<T, TB, 5, kWaves<T>>(g, b, p, out, wts, s);
+        if (nfused == 5) {
+            if (kWide5 && g.ny >= kWide5Rows + 2) return launch_fused<T, TB, 5, 16, kWide5Rows>(g, b, p, out, wts, s);
+            return launch_fused<T, TB, 5, kWaves<T>>(g, b, p, out, wts, s);
+        }
     }
     return hipErrorInvalidValue;
 }

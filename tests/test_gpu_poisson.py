@@ -251,14 +251,16 @@ def test_full_size_sweep_sampled(gpu, dtype, size):
     assert rel_max(got[cells], ref) <= tol * omega
 
 
-@pytest.mark.parametrize("g", [(70, 45, 33, 2.0, 1.5, 1.0), (130, 64, 40, 4.0, 2.0, 2.0), (64, 32, 5, 1.0, 1.0, 1.0)])
+@pytest.mark.parametrize("g", [(70, 45, 33, 2.0, 1.5, 1.0), (130, 64, 40, 4.0, 2.0, 2.0), (64, 32, 5, 1.0, 1.0, 1.0),
+                               (130, 70, 40, 4.0, 2.0, 2.0), (121, 131, 21, 2.0, 2.0, 1.0)])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f16rhs"])
 @pytest.mark.parametrize("nt", [2, 3, 4, 5])
 def test_fused_sweeps_equal_single_sweeps_bitwise(gpu, g, dtype, nt):
     """NT sweeps fused into one launch (LDS tile, z-march) reproduce NT single
     sweeps bit for bit, including ragged tiles, the periodic seams and the
     walls; 2 NT + 1 sweeps also run a shorter remainder launch (FP64 fuses at
-    most 4)."""
+    most 4).  The last two grids (ny >= 66) run five FP32 sweeps on the tall
+    16-wavefront tiles, with ragged last tiles in x and y."""
     import torch
     print(f"fused grid={g} dtype={dtype} nt={nt}", flush=True)
     tdt = torch.float64 if dtype == "f64" else torch.float32
@@ -277,7 +279,8 @@ def test_fused_sweeps_equal_single_sweeps_bitwise(gpu, g, dtype, nt):
 
 
 @pytest.mark.parametrize("dtype,nt,size", [("f32", 4, 512), ("f32", 5, 512), ("f64", 4, 512), ("f32", 4, 1024),
-                                           ("f16rhs", 4, 512)])
+                                           ("f16rhs", 4, 512), ("f16rhs", 5, 512), ("f32", 5, 1024),
+                                           ("f16rhs", 5, 1024)])
 def test_fused_sweeps_full_size_bitwise(gpu, dtype, nt, size):
     """The fused launch at the benchmark grid (512x256x192, the launch
     configuration the bench times: several z-chunks per tile column, ragged
