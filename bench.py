@@ -167,6 +167,15 @@ def fused_depth(acc):
     return -(-acc["sweeps"] // max(acc["launches"], 1))
 
 
+def fused_kernel(acc, ny, rhs="float"):
+    """Name of the FP32 fused relaxation kernel the steps ran: five sweeps
+    run on the 16-wavefront, 64-row tiles where ny >= 66, otherwise on the
+    8-wavefront, 32-row tiles."""
+    d = fused_depth(acc)
+    shape = "16,64" if d == 5 and ny >= 66 else "8"
+    return f"k_relax_fused<float,{rhs},{d},{shape}>"
+
+
 def roofline_from_steps(n, acc, word_bytes, kernel, rhs_bytes=None):
     """Roofline of the dominant kernel from the timed steps: one launch moves
     3 words per cell of compulsory traffic (read p, read b, write p; b takes
@@ -467,7 +476,7 @@ def run_variant(wl, args, name, precision, opt, state=None):
     if precision == "fp64":
         out["relax_kernel"] = roofline_from_steps(n, acc, 8, "k_relax_fused<double,double,{d},16>")
     elif opt.get("rhs16"):
-        out["relax_kernel"] = roofline_from_steps(n, acc, 4, "k_relax_fused<float,_Float16,{d},8>", rhs_bytes=2)
+        out["relax_kernel"] = roofline_from_steps(n, acc, 4, fused_kernel(acc, wl["ny"], "_Float16"), rhs_bytes=2)
     f = fields_of(ch)
     ch.close()
     del ch
@@ -516,7 +525,7 @@ def main():
         fields[name] = f
         if name == "mixed":
             acc_mixed, t_mixed = acc, t
-            roof = roofline_from_steps(n, acc, 4, "k_relax_fused<float,float,{d},8>")
+            roof = roofline_from_steps(n, acc, 4, fused_kernel(acc, wl["ny"]))
             roof["traffic"] = measured_traffic(wl["nx"], wl["ny"], wl["nz"], fused_depth(acc))
             if roof["traffic"]:
                 roof["traffic_over_algorithmic"] = round(roof["traffic"] / (12.0 * n), 3)
