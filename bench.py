@@ -67,7 +67,7 @@ def parse():
 
 
 def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap_order=0, proj_depth=0,
-                 rhs16=0, stencils32=0, state=None):
+                 rhs16=0, stencils32=0, state=None, fixed=False):
     """A context on the workload, started from `state` (device tensors u, v,
     w, p from prepare_state) or, without one, from the laminar profile plus
     the workload's seeded noise."""
@@ -75,7 +75,7 @@ def make_channel(wl, precision, rtol, warm_start=0, learned_correction=0, extrap
     from paper_1511_07800_amd import Channel, inputs
     ch = Channel(wl["nx"], wl["ny"], wl["nz"], wl["lx"], wl["ly"], wl["lz"], nu=wl["nu"], dpdx=wl["dpdx"],
                  dt=wl["dt"], les=wl["les"], cs=wl.get("cs", 0.1), vd_a=wl.get("vd_a", 25.0), precision=precision,
-                 poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=0 if FIXED_CYCLES else 1,
+                 poisson_rtol=rtol, poisson_maxit=200, warm_start=warm_start, srj_adaptive=0 if (FIXED_CYCLES or fixed) else 1,
                  srj_reduction=wl.get("srj_reduction", 1e-3), learned_correction=learned_correction,
                  extrap_order=extrap_order, proj_depth=proj_depth, mixed_rhs16=rhs16, stencils32=stencils32)
     if state is not None:
@@ -427,6 +427,8 @@ VARIANTS = [
     # the same with the eddy viscosity and explicit terms in FP32 (stencils32)
     ("learned_lsq_mixed_rhs16_stencils32", "mixed",
      {"learned": True, "proj_depth": PROJ_DEPTH, "rhs16": 1, "stencils32": 1}),
+    # the paper's method as it stands: FP64 sweeps repeating one fixed cycle
+    ("fp64_fixed_cycle", "fp64", {"fixed": True}),
     ("fp64", "fp64", {}),
 ]
 EXTRA_VARIANTS = [
@@ -451,7 +453,7 @@ def run_variant(wl, args, name, precision, opt, state=None):
                       warm_start=STP_WS_LEARNED if learned else STP_WS_PREV,
                       learned_correction=opt.get("correction", 0), extrap_order=opt.get("extrap_order", 0),
                       proj_depth=opt.get("proj_depth", 0), rhs16=opt.get("rhs16", 0),
-                      stencils32=opt.get("stencils32", 0), state=state)
+                      stencils32=opt.get("stencils32", 0), state=state, fixed=opt.get("fixed", False))
     weights = None
     if learned:
         ch.net_init(training=False)

@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define STP_ABI_VERSION 1
+#define STP_ABI_VERSION 2
 
 typedef struct stp_ctx stp_ctx; /* opaque */
 
@@ -283,11 +283,19 @@ stp_status stp_residual_norm_noalloc(int32_t nx, int32_t ny, int32_t nz, double 
 stp_status stp_lsq_guess(stp_ctx* ctx, int32_t k, const void* const* x_dev, const void* const* y_dev,
                          const void* b_dev, void* out_dev, int32_t* rank);
 
-/* Borrowed view of a field: device pointer, shape {nz or nz+1, ny, nx}
- * (slowest first) and dtype.  STP_W has nz+1 planes.  Every field is FP64,
- * except STP_NUT in the mixed mode, which computes and keeps nu_T in FP32
- * (STP_DTYPE_F32). */
-stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape[3], int32_t* dtype);
+/* Borrowed view of a field on the staggered (MAC) grid of Sec. 3.1: device
+ * pointer, shape {nz or nz+1, ny, nx} (slowest first), strides in elements
+ * in the same order ({nx ny, nx, 1}), dtype, and offset = the position (z, y,
+ * x) of element [0][0][0] in the box [0, lz] x [0, ly] x [0, lx]; element
+ * [k][j][i] lies at offset + (k dz, j dy, i dx):
+ *   STP_U (x-faces)  (dz/2, dy/2, 0)
+ *   STP_V (y-faces)  (dz/2, 0, dx/2)
+ *   STP_W (z-faces)  (0, dy/2, dx/2), nz+1 planes, planes 0 and nz on the walls
+ *   STP_P, STP_NUT, STP_RHS (cell centres)  (dz/2, dy/2, dx/2).
+ * strides and offset may be NULL.  Every field is FP64, except STP_NUT with
+ * stencils32, which computes and keeps nu_T in FP32 (STP_DTYPE_F32). */
+stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape[3], int64_t strides[3],
+                      int32_t* dtype, double offset[3]);
 
 /* Plane averages of the current state at every height, the x-y means from
  * which the paper's space-time averages, bulk velocity, centreline velocity

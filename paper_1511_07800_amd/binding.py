@@ -102,7 +102,8 @@ def load_library():
     L.stp_residual_norm_noalloc.restype = i32
     L.stp_lsq_guess.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, ctypes.POINTER(i32)]
     L.stp_lsq_guess.restype = i32
-    L.stp_fields.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
+    L.stp_fields.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64),
+                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.stp_fields.restype = i32
     L.stp_get_state.argtypes = [vp, ctypes.POINTER(State)]
     L.stp_get_state.restype = i32
@@ -215,17 +216,31 @@ class Channel:
             raise StpError(rc, f"{what}: {msg}")
         return rc
 
-    def field(self, which):
-        """Borrowed torch view of a library field (float64; nu_T is float32 in
-        the mixed mode, as stp_fields reports)."""
+    def field_layout(self, which):
+        """stp_fields' description of a field: device pointer, shape and
+        strides (slowest first), dtype code and the staggered position (z, y,
+        x) of element [0][0][0]."""
         ptr = ctypes.c_void_p()
         shape = (ctypes.c_int64 * 3)()
+        strides = (ctypes.c_int64 * 3)()
+        offset = (ctypes.c_double * 3)()
         dt = ctypes.c_int32()
-        self._check(self.lib.stp_fields(self.handle, which, ctypes.byref(ptr), shape, ctypes.byref(dt)), "stp_fields")
-        n = shape[0] * shape[1] * shape[2]
-        off = ptr.value - self.workspace.data_ptr()
-        tdt, size = {STP_DTYPE_F64: (self.torch.float64, 8), STP_DTYPE_F32: (self.torch.float32, 4)}[dt.value]
-        return self.workspace[off:off + size * n].view(tdt).view(shape[0], shape[1], shape[2])
+        self._check(self.lib.stp_fields(self.handle, which, ctypes.byref(ptr), shape, strides, ctypes.byref(dt),
+                                        offset), "stp_fields")
+        return {"ptr": ptr.value, "shape": tuple(shape), "strides": tuple(strides), "dtype": dt.value,
+                "offset": tuple(offset)}
+
+    def field(self, which):
+        """Borrowed torch view of a library field (float64; nu_T is float32
+        with stencils32, as stp_fields reports), at the returned shape and
+        strides."""
+        lay = self.field_layout(which)
+        shape, strides = lay["shape"], lay["strides"]
+        n = (shape[0] - 1) * strides[0] + (shape[1] - 1) * strides[1] + (shape[2] - 1) * strides[2] + 1
+        off = lay["ptr"] - self.workspace.data_ptr()
+        tdt, size = {STP_DTYPE_F64: (self.torch.float64, 8), STP_DTYPE_F32: (self.torch.float32, 4)}[lay["dtype"]]
+        flat = self.workspace[off:off + size * n].view(tdt)
+        return flat.as_strided(shape, strides)
 
     def checkpoint(self):
         """(copy of the workspace, host state): everything stp_step advances."""

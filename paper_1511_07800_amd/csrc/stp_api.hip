@@ -1242,26 +1242,29 @@ stp_status stp_lsq_guess(stp_ctx* ctx, int32_t k, const void* const* x_dev, cons
     return STP_OK;
 }
 
-stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape[3], int32_t* dtype)
+stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape[3], int64_t strides[3],
+                      int32_t* dtype, double offset[3])
 {
     if (!ctx || !dev_ptr || !shape || !dtype) return STP_EINVAL;
+    const Geo& g = ctx->g;
+    const double dx = ctx->cfg.lx / g.nx, dy = ctx->cfg.ly / g.ny, dz = ctx->cfg.lz / g.nz;
     void* ptr = nullptr;
-    int planes = ctx->g.nz;
+    int planes = g.nz;
+    int32_t dt = STP_DTYPE_F64;
+    // position of element [0][0][0] (z, y, x) on the staggered grid
+    double oz = 0.5 * dz, oy = 0.5 * dy, ox = 0.5 * dx;
     switch (field) {
-    case STP_U: ptr = ctx->u; break;
-    case STP_V: ptr = ctx->v; break;
-    case STP_W: ptr = ctx->w; planes = ctx->g.nz + 1; break;
+    case STP_U: ptr = ctx->u; ox = 0.0; break;
+    case STP_V: ptr = ctx->v; oy = 0.0; break;
+    case STP_W: ptr = ctx->w; planes = g.nz + 1; oz = 0.0; break;
     case STP_P: ptr = ctx->p; break;
     case STP_NUT:
-        if (!ctx->nut) {  // stencils32 keeps nu_T in FP32 only
-            *dev_ptr = ctx->nut32;
-            shape[0] = ctx->g.nz;
-            shape[1] = ctx->g.ny;
-            shape[2] = ctx->g.nx;
-            *dtype = STP_DTYPE_F32;
-            return STP_OK;
+        if (ctx->nut) {
+            ptr = ctx->nut;
+        } else {  // stencils32 keeps nu_T in FP32 only
+            ptr = ctx->nut32;
+            dt = STP_DTYPE_F32;
         }
-        ptr = ctx->nut;
         break;
     case STP_RHS: ptr = ctx->b; break;
     default:
@@ -1270,9 +1273,19 @@ stp_status stp_fields(stp_ctx* ctx, int32_t field, void** dev_ptr, int64_t shape
     }
     *dev_ptr = ptr;
     shape[0] = planes;
-    shape[1] = ctx->g.ny;
-    shape[2] = ctx->g.nx;
-    *dtype = STP_DTYPE_F64;
+    shape[1] = g.ny;
+    shape[2] = g.nx;
+    *dtype = dt;
+    if (strides) {
+        strides[0] = g.plane;
+        strides[1] = g.nx;
+        strides[2] = 1;
+    }
+    if (offset) {
+        offset[0] = oz;
+        offset[1] = oy;
+        offset[2] = ox;
+    }
     return STP_OK;
 }
 

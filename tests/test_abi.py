@@ -80,6 +80,15 @@ def test_workspace_bytes_valid_and_invalid():
     assert lib.stp_workspace_bytes(None) == 0
 
 
+def test_fields_rejects_null_context():
+    from paper_1511_07800_amd import load_library, STP_EINVAL
+    lib = load_library()
+    ptr = ctypes.c_void_p()
+    shape, strides = (ctypes.c_int64 * 3)(), (ctypes.c_int64 * 3)()
+    off, dt = (ctypes.c_double * 3)(), ctypes.c_int32()
+    assert lib.stp_fields(None, 0, ctypes.byref(ptr), shape, strides, ctypes.byref(dt), off) == STP_EINVAL
+
+
 def test_init_rejects_small_workspace_and_null():
     from paper_1511_07800_amd import load_library, STP_EINVAL, STP_ENOMEM
     lib = load_library()

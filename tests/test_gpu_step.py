@@ -164,6 +164,29 @@ def test_phase_times_add_up_to_the_step(gpu, precision):
     ch.close()
 
 
+@pytest.mark.parametrize("st32", [0, 1])
+def test_field_layouts(gpu, st32):
+    """stp_fields describes every field: shape, strides {nx ny, nx, 1}, dtype
+    and the staggered position of element [0][0][0] (Sec. 3.1 MAC grid)."""
+    from paper_1511_07800_amd import (Channel, STP_MIXED, STP_U, STP_V, STP_W, STP_P, STP_NUT, STP_RHS,
+                                      STP_DTYPE_F32, STP_DTYPE_F64)
+    nx, ny, nz, lx, ly, lz = 40, 24, 20, 2.0, 1.2, 2.0
+    dx, dy, dz = lx / nx, ly / ny, lz / nz
+    ch = Channel(nx, ny, nz, lx, ly, lz, nu=1 / 180, dpdx=-1.0, dt=2e-5, les=1, precision=STP_MIXED,
+                 stencils32=st32)
+    want = {STP_U: (nz, (dz / 2, dy / 2, 0.0)), STP_V: (nz, (dz / 2, 0.0, dx / 2)),
+            STP_W: (nz + 1, (0.0, dy / 2, dx / 2)), STP_P: (nz, (dz / 2, dy / 2, dx / 2)),
+            STP_NUT: (nz, (dz / 2, dy / 2, dx / 2)), STP_RHS: (nz, (dz / 2, dy / 2, dx / 2))}
+    for f, (planes, off) in want.items():
+        lay = ch.field_layout(f)
+        assert lay["shape"] == (planes, ny, nx), f
+        assert lay["strides"] == (nx * ny, nx, 1), f
+        assert lay["offset"] == pytest.approx(off, abs=1e-15), f
+        assert lay["dtype"] == (STP_DTYPE_F32 if (f == STP_NUT and st32) else STP_DTYPE_F64), f
+        assert tuple(ch.field(f).shape) == (planes, ny, nx)
+    ch.close()
+
+
 def test_warm_start_zero_same_solution(gpu):
     g = (40, 24, 20, 2.0, 1.2, 2.0)
     nx, ny, nz, lx, ly, lz = g
