@@ -318,6 +318,29 @@ def test_solve_with_fused_sweeps_bitwise(gpu, precision):
     assert torch.equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("g,depth", [((130, 70, 40, 4.0, 2.0, 2.0), 5), ((96, 40, 24, 4.0, 2.0, 2.0), 4),
+                                     ((40, 24, 20, 2.0, 1.2, 2.0), 1)])
+def test_automatic_fusion_depth(gpu, g, depth):
+    """tblock = 0: the mixed solve's FP32 sweeps fuse five per launch where the
+    tall tiles fit (ny >= 66), four on a narrower grid whose launch fits one
+    round of resident workgroups, one where no tile fits; the result equals
+    single sweeps bitwise."""
+    import torch
+    b = to_dev(torch, inputs.poisson_rhs(g[0], g[1], g[2], seed=21))
+    out = []
+    for tb in (0, 1):
+        ch = channel(g, tblock=tb, precision=1)
+        pd = torch.zeros_like(b)
+        stats, rc = ch.poisson_solve(b, pd, 1e-10, 100)
+        assert rc == 0
+        out.append((stats, pd.cpu()))
+    st = out[0][0]
+    print(f"auto depth {g[:3]}: {st['sweeps']} sweeps in {st['launches']} launches", flush=True)
+    assert -(-st["sweeps"] // st["launches"]) == depth
+    assert out[1][0]["launches"] == out[1][0]["sweeps"]
+    assert torch.equal(out[0][1], out[1][1])
+
+
 @pytest.mark.parametrize("g", [GRIDS[0], GRIDS[1], (96, 40, 24, 4.0, 2.0, 2.0)])
 def test_adaptive_solve_matches_oracle(gpu, g):
     """Cycles sized from the reduction still needed: same cycles and sweeps as
